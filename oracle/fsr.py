@@ -1,0 +1,211 @@
+"""Oracle (test infrastructure only): block-wise frequency selective
+reconstruction (FSR), Sec. 2.1, with the recursive use of projected pixels
+of Sec. 3.2 (D-FSR / R-FSR), float64.
+
+The paper describes FSR only at the level of Sec. 2.1: the image is split
+into blocks, each block is modelled in the Fourier domain (where the image is
+assumed approximately sparse) using the samples of neighbouring blocks too,
+and the model is finally overwritten with the available measurements
+(Sec. 3.2).  Concealed weighting is set to zero (Sec. 4), so every block is
+independent.  The FSR internals are the standard greedy (matching-pursuit
+type) FSR of the literature the paper cites; the readings used here:
+
+  * Block b = (bi, bj) covers rows [B*bi, B*bi+B) and columns
+    [B*bj, B*bj+B); its support is the M x M window whose top-left corner is
+    (B*bi - o, B*bj - o), o = (M - B) / 2, so the block sits in the middle.
+  * Weights w[m,n] = a[m,n] * rho ** sqrt((m-c)^2 + (n-c)^2), c = (M-1)/2,
+    with a = 1 for measured pixels, a = pi_w for projected pixels, 0 for
+    unknown pixels and positions outside the frame.
+  * Basis phi_k[m,n] = exp(2*pi*i*(k1*m + k2*n)/M), complex, M x M bins.
+  * Greedy loop, K times, starting from the residual r = s and c = 0:
+      R   = sum_{m} w[m] r[m] conj(phi_k[m])         (the weighted residual DFT)
+      b   = first argmax_k |R_k|^2 in row-major order
+      dlt = gamma * R_b / W0,  W0 = sum w           (orthogonality-deficiency
+                                                     compensation gamma)
+      c_b += dlt ;  r -= dlt * phi_b
+  * Model g = sum_k c_k phi_k; the block output is Re g on the block pixels.
+  * Overwrite: D-FSR writes the measured values over the model, R-FSR the
+    measured and the projected values (Sec. 3.2).
+  * No frequency-weighting prior, no early stop; W0 = 0 gives g = 0.
+
+Two forms are given: `fsr_spatial` recomputes the weighted residual DFT from
+the spatial residual every iteration (the plain form), `fsr_spectral`
+updates the residual spectrum in place (R_k -= dlt * W_{k-b}, W = DFT(w)).
+They must agree to rounding.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rho_table(rho: float, M: int = 32) -> np.ndarray:
+    """Isotropic decay rho ** distance-to-support-centre, (M, M) float64."""
+    c = (M - 1) / 2.0
+    m = np.arange(M, dtype=np.float64)
+    d = np.sqrt((m[:, None] - c) ** 2 + (m[None, :] - c) ** 2)
+    return rho ** d
+
+
+def _basis(b1, b2, M):
+    """phi_b[m,n] = exp(2 pi i b1 m / M) * exp(2 pi i b2 n / M)."""
+    m = np.arange(M, dtype=np.float64)
+    e1 = np.exp(2j * np.pi * b1[:, None] * m[None, :] / M)
+    e2 = np.exp(2j * np.pi * b2[:, None] * m[None, :] / M)
+    return e1[:, :, None] * e2[:, None, :]
+
+
+def fsr_spatial(s, w, gamma, K, track_gaps=False):
+    """Greedy FSR on a batch of supports (independent blocks).
+
+    s: (nb, M, M) real or complex samples (0 where unknown), w: (nb, M, M)
+    real weights.  Returns (c (nb,M,M) complex coefficients,
+    picks (nb,K) flat bin indices, gaps (nb,) or None, (energies, chosen)):
+    energies[i] = sum w |r|^2 after iteration i, chosen[i] = |R_b|^2 of the
+    bin chosen at iteration i.
+
+    With track_gaps, gaps[b] is the minimum over iterations of
+    (E_best - E_next) / E_best, where E_next excludes the chosen bin and,
+    while the residual spectrum is Hermitian (real data and only
+    self-conjugate bins chosen so far), also its conjugate partner: choosing
+    the partner then gives the conjugate trajectory and the same real model.
+    """
+    s = np.asarray(s)
+    w = np.asarray(w, np.float64)
+    nb, M, _ = w.shape
+    idx = np.arange(nb)
+    r = s.astype(np.complex128).copy()
+    c = np.zeros((nb, M * M), np.complex128)
+    W0 = w.sum(axis=(1, 2))
+    safe = W0 > 0
+    picks = np.zeros((nb, K), np.int64)
+    gaps = np.full(nb, np.inf) if track_gaps else None
+    herm = np.full(nb, bool(np.isrealobj(s) or not np.any(np.imag(s))))
+    energies = []      # weighted residual energy sum w|r|^2 after each iteration
+    chosen = []        # |R_b|^2 of the chosen bin at each iteration
+    for it in range(K):
+        Rs = np.fft.fft2(w * r).reshape(nb, M * M)
+        E = Rs.real ** 2 + Rs.imag ** 2
+        b = E.argmax(axis=1)
+        picks[:, it] = b
+        Rb = Rs[idx, b]
+        chosen.append(E[idx, b])
+        dlt = np.where(safe, gamma * Rb / np.where(safe, W0, 1.0), 0.0)
+        c[idx, b] += dlt
+        b1, b2 = b // M, b % M
+        r -= dlt[:, None, None] * _basis(b1, b2, M)
+        if track_gaps:
+            E1 = E[idx, b]
+            Es = E.copy()
+            Es[idx, b] = -np.inf
+            partner = ((-b1) % M) * M + ((-b2) % M)
+            hp = herm & (partner != b)
+            Es[idx[hp], partner[hp]] = -np.inf
+            E2 = Es.max(axis=1)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                g = np.where(E1 > 0, (E1 - E2) / E1, np.inf)
+            gaps = np.minimum(gaps, g)
+            herm &= partner == b
+        energies.append((w * np.abs(r) ** 2).sum(axis=(1, 2)))
+    return c.reshape(nb, M, M), picks, gaps, (energies, chosen)
+
+
+def fsr_spectral(s, w, gamma, K):
+    """Same loop with an in-place residual-spectrum update
+    R_k <- R_k - dlt * W_{(k-b) mod M}.  Returns (c, picks)."""
+    s = np.asarray(s)
+    w = np.asarray(w, np.float64)
+    nb, M, _ = w.shape
+    idx = np.arange(nb)
+    R = np.fft.fft2(w * s.astype(np.complex128))
+    Wsp = np.fft.fft2(w)
+    W0 = w.sum(axis=(1, 2))
+    safe = W0 > 0
+    c = np.zeros((nb, M * M), np.complex128)
+    picks = np.zeros((nb, K), np.int64)
+    m = np.arange(M)
+    for it in range(K):
+        Rf = R.reshape(nb, M * M)
+        E = Rf.real ** 2 + Rf.imag ** 2
+        b = E.argmax(axis=1)
+        picks[:, it] = b
+        dlt = np.where(safe, gamma * Rf[idx, b] / np.where(safe, W0, 1.0), 0.0)
+        c[idx, b] += dlt
+        b1, b2 = b // M, b % M
+        i1 = (m[None, :] - b1[:, None]) % M
+        i2 = (m[None, :] - b2[:, None]) % M
+        R = R - dlt[:, None, None] * Wsp[idx[:, None, None], i1[:, :, None], i2[:, None, :]]
+    return c.reshape(nb, M, M), picks
+
+
+def synthesize(c, B):
+    """Block output Re(sum_k c_k phi_k) on the B x B block pixels."""
+    nb, M, _ = c.shape
+    g = (M * M) * np.fft.ifft2(c)
+    o = (M - B) // 2
+    return g[:, o:o + B, o:o + B].real
+
+
+def class_weight(cls, proj_weight):
+    """a = 1 measured, pi_w projected, 0 unknown."""
+    return np.where(cls == 1, 1.0, np.where(cls == 2, proj_weight, 0.0))
+
+
+def gather_supports(values, cls, blocks, B=4, M=32, proj_weight=1.0):
+    """Samples and class weights on the supports of the listed blocks.
+
+    blocks: (nb, 2) int block indices (bi, bj).  Positions outside the frame
+    and unknown positions get weight 0 and sample 0 (never read)."""
+    H, W = values.shape
+    o = (M - B) // 2
+    a = class_weight(cls, proj_weight)
+    v = np.where(cls > 0, values, 0.0)
+    pad_lo, pad_hi = o, M - B - o
+    vp = np.pad(v, ((pad_lo, pad_hi + B), (pad_lo, pad_hi + B)))
+    ap = np.pad(a, ((pad_lo, pad_hi + B), (pad_lo, pad_hi + B)))
+    blocks = np.asarray(blocks, np.int64).reshape(-1, 2)
+    nb = blocks.shape[0]
+    s = np.empty((nb, M, M))
+    aw = np.empty((nb, M, M))
+    for i, (bi, bj) in enumerate(blocks):
+        y0, x0 = B * bi, B * bj   # = (B*bi - o) + pad_lo
+        s[i] = vp[y0:y0 + M, x0:x0 + M]
+        aw[i] = ap[y0:y0 + M, x0:x0 + M]
+    return s, aw
+
+
+def fsr_blocks_out(values, cls, blocks, B=4, M=32, rho=0.7, gamma=0.5, K=100,
+                   proj_weight=1.0, overwrite="dfsr", track_gaps=True, chunk=2048):
+    """FSR of the listed blocks.  Returns (out (nb,B,B) float64, gaps (nb,))."""
+    blocks = np.asarray(blocks, np.int64).reshape(-1, 2)
+    tab = rho_table(rho, M)
+    outs, gaps = [], []
+    for i in range(0, blocks.shape[0], chunk):
+        blk = blocks[i:i + chunk]
+        s, a = gather_supports(values, cls, blk, B, M, proj_weight)
+        c, _, g, _ = fsr_spatial(s, a * tab[None], gamma, K, track_gaps=track_gaps)
+        out = synthesize(c, B)
+        # overwrite with measured (D-FSR) or measured + projected (R-FSR) values
+        for j, (bi, bj) in enumerate(blk):
+            cb = cls[B * bi:B * bi + B, B * bj:B * bj + B]
+            vb = values[B * bi:B * bi + B, B * bj:B * bj + B]
+            keep = (cb == 1) if overwrite == "dfsr" else (cb >= 1)
+            out[j][keep] = vb[keep]
+        outs.append(out)
+        gaps.append(g if g is not None else np.full(blk.shape[0], np.inf))
+    return np.concatenate(outs), np.concatenate(gaps)
+
+
+def all_blocks(H, W, B=4):
+    bi, bj = np.mgrid[0:H // B, 0:W // B]
+    return np.stack([bi.ravel(), bj.ravel()], axis=1)
+
+
+def fsr_frame(values, cls, B=4, M=32, rho=0.7, gamma=0.5, K=100, proj_weight=1.0,
+              overwrite="dfsr", track_gaps=True):
+    """FSR of a whole frame.  Returns (out (H,W) float64, gaps (H/B, W/B))."""
+    H, W = values.shape
+    blocks = all_blocks(H, W, B)
+    out_b, gaps = fsr_blocks_out(values, cls, blocks, B, M, rho, gamma, K, proj_weight,
+                                 overwrite, track_gaps)
+    out = out_b.reshape(H // B, W // B, B, B).transpose(0, 2, 1, 3).reshape(H, W)
+    return out, gaps.reshape(H // B, W // B)

@@ -1,0 +1,164 @@
+"""Pins of the oracle's FSR (Sec. 2.1 / 3.2): closed forms for inputs made of
+a single basis function, the exact per-iteration energy decrement of the
+greedy update, agreement of the two independently written forms (re-FFT of
+the spatial residual vs in-place spectral update), exact scale and
+translation equivariance, the overwrite rule and garbage invariance."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import fsr as F
+import synth
+
+M = 32
+
+
+def quarter_weights(rng, rho=0.7):
+    m = synth.fixed_mask(M, M, rng).astype(np.float64)
+    return m * O.rho_table(rho, M)
+
+
+@pytest.mark.parametrize("K", [1, 7, 100])
+def test_constant_block_closed_form(K):
+    """s = c * phi_0: DC is chosen every iteration (|W_k| < W_0 for k != 0
+    off a lattice coset), c_0 = c (1 - (1-gamma)^K)."""
+    rng = np.random.default_rng(K)
+    w = quarter_weights(rng)[None]
+    s = np.full((1, M, M), 100.0)
+    c, picks, _, _ = F.fsr_spatial(s, w, 0.5, K)
+    expect = 100.0 * (1 - 0.5 ** K)
+    assert abs(c[0, 0, 0] - expect) < 1e-9
+    out = F.synthesize(c, 4)
+    assert np.allclose(out, expect, atol=1e-9, rtol=0)
+
+
+@pytest.mark.parametrize("b", [(3, 5), (5, 3), (16, 0), (31, 1)])
+def test_single_complex_bin_closed_form(b):
+    """s = z * phi_b (complex): coefficient z (1 - (1-gamma)^K) at bin b and
+    the model is that multiple of phi_b.  Catches a swapped index, a wrong
+    exponent sign, a missing gamma or W0."""
+    rng = np.random.default_rng(sum(b))
+    w = quarter_weights(rng)[None]
+    m = np.arange(M)
+    z = 3.0 - 7.0j
+    phi = np.exp(2j * np.pi * (b[0] * m[:, None] + b[1] * m[None, :]) / M)
+    for K, g in ((10, 0.5), (40, 0.3)):
+        c, picks, _, _ = F.fsr_spatial((z * phi)[None], w, g, K)
+        assert (picks[0, :5] == b[0] * M + b[1]).all()
+        expect = z * (1 - (1 - g) ** K)
+        assert abs(c[0, b[0], b[1]] - expect) < 1e-12 * abs(z)
+        g_model = (M * M) * np.fft.ifft2(c[0])
+        assert np.allclose(g_model, expect * phi, atol=1e-10)
+
+
+def test_energy_decrement_identity():
+    """E' = E - gamma (2 - gamma) |R_b|^2 / W0 with E = sum w |r|^2:
+    exact for this update, so it is checked to rounding each iteration."""
+    rng = np.random.default_rng(5)
+    nb = 6
+    w = np.stack([quarter_weights(rng) for _ in range(nb)])
+    s = rng.uniform(0, 255, (nb, M, M))
+    for g in (0.5, 1.0, 1.7):
+        c, picks, _, (energies, chosen) = F.fsr_spatial(s, w, g, 60)
+        W0 = w.sum(axis=(1, 2))
+        E_prev = (w * s ** 2).sum(axis=(1, 2))
+        for it in range(60):
+            pred = E_prev - g * (2 - g) * chosen[it] / W0
+            assert np.allclose(energies[it], pred, rtol=1e-9, atol=1e-9 * E_prev.max())
+            assert (energies[it] <= E_prev * (1 + 1e-12)).all()     # monotone
+            E_prev = energies[it]
+
+
+def test_spatial_and_spectral_forms_agree():
+    rng = np.random.default_rng(6)
+    nb = 8
+    w = np.stack([quarter_weights(rng) for _ in range(nb)])
+    s = rng.uniform(0, 255, (nb, M, M)) * (w > 0)
+    c1, p1, _, _ = F.fsr_spatial(s, w, 0.5, 50)
+    c2, p2 = F.fsr_spectral(s, w, 0.5, 50)
+    # picks agree up to the conjugate-partner tie of real data: where the two
+    # forms round a tie differently they follow conjugate trajectories
+    conj = lambda p: ((-(p // M)) % M) * M + (-(p % M)) % M
+    assert ((p1 == p2) | (p1 == conj(p2))).all()
+    o1, o2 = F.synthesize(c1, 4), F.synthesize(c2, 4)
+    assert np.max(np.abs(o1 - o2)) < 1e-9
+
+
+def _frame(seed, H=48, W=56, kind="dynamic"):
+    rng = np.random.default_rng(seed)
+    f = synth.video_regions(1, H, W, rng, grid=2, vmax=1)[0]
+    m = synth.mask_sequence(kind, 1, H, W, rng)[0]
+    return f, m, synth.measured(f, m)
+
+
+def test_scale_equivariance_exact():
+    f, m, meas = _frame(1)
+    v = meas.astype(np.float64)
+    o1, _ = O.fsr_frame(v, m, K=30)
+    o2, _ = O.fsr_frame(2.0 * v, m, K=30)
+    assert (o2 == 2.0 * o1).all()       # power-of-two scaling commutes with rounding
+    o3, _ = O.fsr_frame(3.0 * v, m, K=30)
+    assert np.max(np.abs(o3 - 3.0 * o1)) < 1e-9 * 255
+
+
+def test_translation_by_block_multiples():
+    """Shifting frame and mask by a multiple of the block size shifts the
+    output of every block whose support lies inside both frames, bitwise."""
+    f, m, meas = _frame(2, 64, 64)
+    v = meas.astype(np.float64)
+    o1, _ = O.fsr_frame(v, m, K=20)
+    v2 = np.zeros_like(v)
+    m2 = np.zeros_like(m)
+    v2[4:, 8:] = v[:-4, :-8]
+    m2[4:, 8:] = m[:-4, :-8]
+    o2, _ = O.fsr_frame(v2, m2, K=20)
+    # blocks with supports inside both: rows 32..44 of frame 2 map to 28..40 of frame 1
+    assert (o2[32:36, 32:36] == o1[28:32, 24:28]).all()
+
+
+def test_overwrite_and_garbage_invariance():
+    f, m, meas = _frame(3)
+    v = meas.astype(np.float64)
+    cls = m.copy()
+    o, _ = O.fsr_frame(v, cls, K=20)
+    assert (o[m == 1] == v[m == 1]).all()
+    vg = v.copy()
+    vg[m == 0] = np.nan
+    og, _ = O.fsr_frame(vg, cls, K=20)
+    assert (og == o).all()
+    # projected pixels: modelled but not overwritten by D-FSR, overwritten by R-FSR
+    cls2 = cls.copy()
+    rng = np.random.default_rng(0)
+    proj = (m == 0) & (rng.random(m.shape) < 0.3)
+    cls2[proj] = 2
+    v2 = v.copy()
+    v2[proj] = f[proj]
+    od, _ = O.fsr_frame(v2, cls2, K=20, overwrite="dfsr")
+    orr, _ = O.fsr_frame(v2, cls2, K=20, overwrite="rfsr")
+    assert (orr[proj] == v2[proj]).all()
+    assert not (od[proj] == v2[proj]).all()
+    assert (od[m == 1] == v[m == 1]).all()
+    # projected samples help: closer to the truth than without them
+    assert np.abs(od - f)[m == 0].mean() < np.abs(o - f)[m == 0].mean()
+
+
+def test_no_samples_gives_zero_model():
+    v = np.zeros((8, 8))
+    cls = np.zeros((8, 8), np.uint8)
+    o, _ = O.fsr_frame(v, cls, K=5)
+    assert (o == 0).all()
+
+
+def test_near_tie_gap_conjugate_rule():
+    """For real data the spectrum is Hermitian until a non-self-conjugate
+    bin is chosen, so that choice ties with its conjugate partner; the gap
+    measure must exclude the partner (else every block would look tied)."""
+    rng = np.random.default_rng(8)
+    w = quarter_weights(rng)[None]
+    s = (rng.uniform(0, 255, (M, M)) * (w[0] > 0))[None]
+    c, picks, gaps, (_, chosen) = F.fsr_spatial(s, w, 0.5, 30, track_gaps=True)
+    first = next(i for i in range(30) if picks[0, i] != 0)
+    b = picks[0, first]
+    partner = ((-(b // M)) % M) * M + (-(b % M)) % M
+    assert partner != b
+    assert gaps[0] > 1e-6
