@@ -1,0 +1,193 @@
+/*
+ * rfsr.h - C ABI of the MI355X (gfx950) library for recursive frequency
+ * selective reconstruction (FSR) of quarter-sampled video with fast motion
+ * consistency checks (Grosche, Seiler, Kaup, ICIP 2021).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every image pointer is a DEVICE pointer owned by the caller.  Planes are
+ *    row-major H x W with a row stride `pitch` given in ELEMENTS of the
+ *    plane's own type (pitch >= W); all planes of one call share `pitch`.
+ *  - The library allocates no device memory.  Scratch space is the caller's
+ *    `workspace` (device, >= rfsr_workspace_bytes(...) bytes, 256-byte
+ *    aligned); its contents on entry are irrelevant and on exit undefined.
+ *  - All work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *    void*; NULL is the default stream).  The return value reports argument
+ *    validation and launch errors synchronously; a device fault of this call
+ *    surfaces at the caller's next synchronisation.
+ *  - H and W must be positive multiples of 4 (the FSR block size, hence also
+ *    of the 2x2 quarter-sampling cell) and at most 16384.
+ *  - Masks hold 0 (not measured) or 1 (measured).  Measured-frame values at
+ *    unmeasured positions are never read, so they may hold anything.
+ *  - Motion vectors are (alpha, beta) = (row offset, column offset), int8.
+ *  - Calls on different streams do not share state and may run concurrently
+ *    as long as their workspaces differ.
+ */
+#ifndef RFSR_H
+#define RFSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RFSR_OK = 0,
+    RFSR_EINVAL = -1,        /* null pointer or parameter out of range          */
+    RFSR_ESHAPE = -2,        /* H, W or pitch not supported                     */
+    RFSR_EWORKSPACE = -3,    /* workspace null, too small or misaligned         */
+    RFSR_EDEVICE = -4,       /* HIP runtime error (no device, launch failure)   */
+    RFSR_EUNSUPPORTED = -5   /* valid request this build does not implement     */
+} rfsr_status;
+
+/* Consistency check applied to the forward motion field.
+ *   NONE      every vector accepted.
+ *   RME       reverse motion estimation: accept iff the reverse vector at
+ *             q = p + v equals -v (Sec. 2.2, the literature check).
+ *   RMC       reverse motion check: accept iff the back-pointing candidate
+ *             has strictly the lowest normalised cost among the reverse
+ *             candidates [-rmc_radius, rmc_radius]^2 placed symmetrically
+ *             around it (Sec. 3.1.1, Fig. 2b).
+ *   FRMC      the same test with offsets {-7,-3,-1,0,1,3,7}^2 (Sec. 3.1.1,
+ *             Fig. 2c).
+ *   NNC       nearest-neighbour check on the 3x3 median filtered field
+ *             (Sec. 3.1.2, Eq. (1), Fig. 2d).
+ *   NNC_FRMC  NNC, then FRMC only where NNC accepted (Sec. 3.1.2, Table 3). */
+typedef enum {
+    RFSR_CHECK_NONE = 0,
+    RFSR_CHECK_RME = 1,
+    RFSR_CHECK_RMC = 2,
+    RFSR_CHECK_FRMC = 3,
+    RFSR_CHECK_NNC = 4,
+    RFSR_CHECK_NNC_FRMC = 5
+} rfsr_check;
+
+/* Final overwrite of the FSR model (Sec. 3.2): D-FSR writes only measured
+ * pixels over the model, R-FSR writes measured and projected pixels. */
+typedef enum { RFSR_DFSR = 0, RFSR_RFSR = 1 } rfsr_overwrite;
+
+/* Motion estimation by pixel-wise template matching (Sec. 2.2).
+ * Cost of vector v at pixel p, template offsets D = {-1,0,1,2}^2:
+ *   S(p,v) = sum_{d in D, p+d in frame} b_t(p+d) |f_t(p+d) - Rhat(clamp(p+d+v))|
+ * minimised over v in [-search, search]^2 with p+v in the frame, with the
+ * total order (S, |v|_1, raster index of v).  Reverse costs are compared
+ * normalised by the number of measured template pixels. */
+typedef struct {
+    int32_t tmpl;        /* template size; this build supports 4             */
+    int32_t search;      /* search radius R, 0..15                            */
+    int32_t check;       /* rfsr_check                                        */
+    int32_t rmc_radius;  /* RMC radius, 0..15; 0 selects `search`             */
+} rfsr_me_params;
+
+/* Block-wise FSR (Sec. 2.1) with concealed weighting 0 (Sec. 4), so blocks
+ * are independent.  Each B x B block is modelled on the M x M support
+ * centred on it by K greedy iterations over the M x M complex DFT basis:
+ * pick the bin with the largest weighted residual energy, add
+ * gamma * R_b / W0 to its coefficient, subtract it from the residual.
+ * Weights: a * rho^(distance to the support centre), a = 1 measured,
+ * proj_weight projected, 0 unknown / outside the frame.  The transform, the
+ * residual spectrum and its energies are kept in float64 (full-rate on the
+ * CDNA4 vector ALU); float32 drifts past the 1e-3 output tolerance within
+ * 100 iterations. */
+typedef struct {
+    int32_t block;       /* B; this build supports 4                          */
+    int32_t support;     /* M; this build supports 32                         */
+    int32_t iters;       /* K, 0..1024                                        */
+    int32_t overwrite;   /* rfsr_overwrite                                    */
+    double rho;          /* 0 < rho <= 1                                      */
+    double gamma;        /* 0 < gamma < 2                                     */
+    double proj_weight;  /* >= 0, weight of projected samples                 */
+} rfsr_fsr_params;
+
+/* Indices into the optional counters array of rfsr_motion_check. */
+enum {
+    RFSR_CNT_FORWARD_COSTS = 0,   /* forward template costs evaluated          */
+    RFSR_CNT_CHECK_COSTS = 1,     /* reverse template costs evaluated by the
+                                     check (RME, RMC, FRMC; FRMC/RMC stop at
+                                     the first losing candidate)               */
+    RFSR_CNT_CHECKED_PIXELS = 2,  /* pixels that entered the RMC/FRMC test     */
+    RFSR_CNT_ACCEPTED = 3,        /* accepted pixels                           */
+    RFSR_NCOUNTERS = 4
+};
+
+/* Bytes of workspace sufficient for any call of this library on an H x W
+ * frame with up to `nref` references (0..3) and these parameters.
+ * Returns 0 if the arguments are invalid. */
+size_t rfsr_workspace_bytes(int32_t H, int32_t W, int32_t nref,
+                            const rfsr_me_params* me, const rfsr_fsr_params* fsr);
+
+/* Forward motion estimation of the current frame against one reference
+ * reconstruction, followed by the consistency check `me->check`
+ * (Sec. 2.2, Sec. 3.1).
+ *   cur        uint8 H x W measured frame f_t (read only where cur_mask==1)
+ *   cur_mask   uint8 H x W mask b_t
+ *   ref_recon  uint8 H x W reconstruction of the past frame
+ *   mv         int8 [2][H][W] out: plane 0 alpha (rows), plane 1 beta (cols);
+ *              plane 1 starts at mv + H*pitch
+ *   accept     uint8 H x W out: 1 accepted, 0 rejected
+ *   cost       uint16 H x W out (nullable): S of the chosen vector
+ *   counters   uint64 [RFSR_NCOUNTERS] (nullable): ADDED to (caller zeroes)
+ * Errors: RFSR_EINVAL (null input/output, bad params), RFSR_ESHAPE,
+ * RFSR_EWORKSPACE, RFSR_EUNSUPPORTED (tmpl != 4), RFSR_EDEVICE. */
+rfsr_status rfsr_motion_check(const uint8_t* cur, const uint8_t* cur_mask,
+                              const uint8_t* ref_recon, int32_t H, int32_t W,
+                              int64_t pitch, const rfsr_me_params* me,
+                              int8_t* mv, uint8_t* accept, uint16_t* cost,
+                              unsigned long long* counters,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/* Block-parallel FSR of one frame (Sec. 2.1; Sec. 3.2 for classes).
+ *   values  float32 H x W sample values, read only where cls > 0
+ *   cls     uint8 H x W: 0 unknown, 1 measured, 2 projected (others = 0)
+ *   out     float32 H x W out: Re of the model, then the overwrite rule;
+ *           not clamped
+ *   out_u8  uint8 H x W out (nullable): rint(clamp(out, 0, 255)), ties to even
+ * Errors: RFSR_EINVAL, RFSR_ESHAPE, RFSR_EWORKSPACE, RFSR_EUNSUPPORTED
+ * (block != 4 or support != 32), RFSR_EDEVICE. */
+rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32_t W,
+                       int64_t pitch, const rfsr_fsr_params* fsr,
+                       float* out, uint8_t* out_u8,
+                       void* workspace, size_t ws_bytes, void* stream);
+
+/* One recursive D-FSR / R-FSR frame in the order of Fig. 1: for each of the
+ * nref (0..3) references, forward ME against its reconstruction and the
+ * consistency check; projection of the measured reference pixels that the
+ * accepted vectors point to (averaged over references, Sec. 2.2); FSR with
+ * measured and projected samples; overwrite; quantisation.
+ *   ref_recon, ref_meas, ref_mask: HOST arrays of nref device pointers,
+ *     index k = lag k+1 (uint8 H x W each; ref_meas read only where
+ *     ref_mask == 1).  May be NULL when nref == 0 (single-frame FSR).
+ *   out     float32 H x W out; out_u8 uint8 H x W out (nullable)
+ *   stage_events: NULL, or a HOST array of 4 events (from rfsr_event_create)
+ *     recorded on `stream` at: [0] start, [1] after ME and checks,
+ *     [2] after projection, [3] after FSR.
+ * Errors: as rfsr_motion_check and fsr_blocks. */
+rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
+                                   const uint8_t* const* ref_recon,
+                                   const uint8_t* const* ref_meas,
+                                   const uint8_t* const* ref_mask,
+                                   int32_t H, int32_t W, int64_t pitch,
+                                   const rfsr_me_params* me, const rfsr_fsr_params* fsr,
+                                   float* out, uint8_t* out_u8, void* const* stage_events,
+                                   void* workspace, size_t ws_bytes, void* stream);
+
+/* Timing events for stage_events and benchmarks (thin wrappers of HIP
+ * events).  rfsr_event_elapsed_ms waits for `stop`. */
+rfsr_status rfsr_event_create(void** event);
+rfsr_status rfsr_event_destroy(void* event);
+rfsr_status rfsr_event_record(void* event, void* stream);
+rfsr_status rfsr_event_elapsed_ms(void* start, void* stop, float* ms);
+
+/* Human-readable name of a status code (static storage). */
+const char* rfsr_status_string(int32_t status);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t rfsr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFSR_H */

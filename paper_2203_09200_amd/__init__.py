@@ -1,0 +1,14 @@
+"""MI355X (gfx950) implementation of recursive frequency selective
+reconstruction of quarter-sampled video with fast motion consistency checks
+(Grosche, Seiler, Kaup, ICIP 2021).
+
+The computation lives in librfsr.so (HIP kernels behind the C ABI of
+include/rfsr.h); this package is its Python binding.
+"""
+from ._lib import (CHECKS, COUNTER_NAMES, Event, FSRParams, MEParams, RfsrError, Sequence,
+                   Workspace, fsr_blocks, lib, motion_check, reconstruct_frame, workspace_bytes,
+                   LIB_PATH)
+
+__all__ = ["CHECKS", "COUNTER_NAMES", "Event", "FSRParams", "MEParams", "RfsrError", "Sequence",
+           "Workspace", "fsr_blocks", "lib", "motion_check", "reconstruct_frame",
+           "workspace_bytes", "LIB_PATH"]

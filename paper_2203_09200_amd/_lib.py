@@ -1,0 +1,320 @@
+"""ctypes binding of librfsr.so.
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels behind the C ABI declared in include/rfsr.h.  Torch tensors provide
+device memory and the current stream.  There is no fallback: if the library
+is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librfsr.so")
+
+CHECKS = {"none": 0, "rme": 1, "rmc": 2, "frmc": 3, "nnc": 4, "nnc_frmc": 5}
+OVERWRITE = {"dfsr": 0, "rfsr": 1}
+NCOUNTERS = 4
+COUNTER_NAMES = ("forward_costs", "check_costs", "checked_pixels", "accepted")
+
+
+class RfsrError(RuntimeError):
+    pass
+
+
+class _MEParams(ctypes.Structure):
+    _fields_ = [("tmpl", ctypes.c_int32), ("search", ctypes.c_int32),
+                ("check", ctypes.c_int32), ("rmc_radius", ctypes.c_int32)]
+
+
+class _FSRParams(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("support", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("overwrite", ctypes.c_int32),
+                ("rho", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("proj_weight", ctypes.c_double)]
+
+
+@dataclass
+class MEParams:
+    """Motion estimation and consistency check (Sec. 2.2, Sec. 3.1)."""
+    search: int = 9
+    check: str = "nnc_frmc"
+    rmc_radius: int = 0
+    tmpl: int = 4
+
+    def c(self) -> _MEParams:
+        return _MEParams(self.tmpl, self.search, CHECKS[self.check], self.rmc_radius)
+
+
+@dataclass
+class FSRParams:
+    """Block-wise FSR (Sec. 2.1, Sec. 3.2)."""
+    iters: int = 100
+    rho: float = 0.7
+    gamma: float = 0.5
+    proj_weight: float = 1.0
+    overwrite: str = "dfsr"
+    block: int = 4
+    support: int = 32
+
+    def c(self) -> _FSRParams:
+        return _FSRParams(self.block, self.support, self.iters, OVERWRITE[self.overwrite],
+                          self.rho, self.gamma, self.proj_weight)
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_STATUS = ctypes.c_int32
+
+
+def lib():
+    """Load librfsr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RfsrError(f"{LIB_PATH} not built; run `python -m paper_2203_09200_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.rfsr_workspace_bytes.restype = ctypes.c_size_t
+    L.rfsr_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(_MEParams), ctypes.POINTER(_FSRParams)]
+    L.rfsr_motion_check.restype = _STATUS
+    L.rfsr_motion_check.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                    ctypes.POINTER(_MEParams), _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    L.fsr_blocks.restype = _STATUS
+    L.fsr_blocks.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                             ctypes.POINTER(_FSRParams), _P, _P, _P, ctypes.c_size_t, _P]
+    L.rfsr_reconstruct_frame.restype = _STATUS
+    L.rfsr_reconstruct_frame.argtypes = [_P, _P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                         ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.POINTER(_MEParams),
+                                         ctypes.POINTER(_FSRParams), _P, _P, ctypes.POINTER(_P),
+                                         _P, ctypes.c_size_t, _P]
+    L.rfsr_event_create.restype = _STATUS
+    L.rfsr_event_create.argtypes = [ctypes.POINTER(_P)]
+    L.rfsr_event_destroy.restype = _STATUS
+    L.rfsr_event_destroy.argtypes = [_P]
+    L.rfsr_event_record.restype = _STATUS
+    L.rfsr_event_record.argtypes = [_P, _P]
+    L.rfsr_event_elapsed_ms.restype = _STATUS
+    L.rfsr_event_elapsed_ms.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_float)]
+    L.rfsr_status_string.restype = ctypes.c_char_p
+    L.rfsr_status_string.argtypes = [ctypes.c_int32]
+    L.rfsr_version.restype = ctypes.c_int32
+    L.rfsr_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = lib().rfsr_status_string(status).decode()
+        raise RfsrError(f"{what} failed: {msg} ({status})")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _plane(t, dtype, name, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise RfsrError(f"{name}: expected a device tensor")
+    if t.dtype != dtype:
+        raise RfsrError(f"{name}: expected {dtype}, got {t.dtype}")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise RfsrError(f"{name}: expected a 2-D row-major plane")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise RfsrError(f"{name}: expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+def workspace_bytes(H, W, nref=3, me: MEParams | None = None, fsr: FSRParams | None = None) -> int:
+    mc = me.c() if me else None
+    fc = fsr.c() if fsr else None
+    n = lib().rfsr_workspace_bytes(H, W, nref, ctypes.byref(mc) if mc else None,
+                                   ctypes.byref(fc) if fc else None)
+    if n == 0:
+        raise RfsrError("invalid arguments for rfsr_workspace_bytes")
+    return int(n)
+
+
+class Workspace:
+    """Device scratch buffer reused across calls (grown on demand)."""
+
+    def __init__(self, device=None):
+        self.device = device or torch.device("cuda")
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            if self.buf.data_ptr() % 256:
+                raise RfsrError("workspace allocation is not 256-byte aligned")
+        return self.buf
+
+
+_default_ws = {}
+
+
+def _ws(workspace, device, nbytes):
+    if workspace is None:
+        key = str(device)
+        workspace = _default_ws.setdefault(key, Workspace(device))
+    return workspace.get(nbytes)
+
+
+def motion_check(cur, cur_mask, ref_recon, me: MEParams | None = None, counters=None,
+                 want_cost=True, workspace: Workspace | None = None, stream=None):
+    """Forward ME of `cur` against `ref_recon` plus the consistency check.
+
+    Returns (mv int8 (2,H,W), accept uint8 (H,W), cost int16 (H,W) or None).
+    `counters`: optional int64 device tensor of 4 entries, added to.
+    """
+    me = me or MEParams()
+    _plane(cur, torch.uint8, "cur")
+    H, W = cur.shape
+    _plane(cur_mask, torch.uint8, "cur_mask", (H, W))
+    _plane(ref_recon, torch.uint8, "ref_recon", (H, W))
+    if not (cur.stride(0) == cur_mask.stride(0) == ref_recon.stride(0) == W):
+        raise RfsrError("motion_check: inputs must be contiguous")
+    dev = cur.device
+    mv = torch.empty((2, H, W), dtype=torch.int8, device=dev)
+    acc = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    cost = torch.empty((H, W), dtype=torch.int16, device=dev) if want_cost else None
+    if counters is not None and (counters.dtype != torch.int64 or counters.numel() < NCOUNTERS
+                                 or not counters.is_cuda):
+        raise RfsrError("counters: expected int64 device tensor with 4 entries")
+    mc = me.c()
+    nbytes = workspace_bytes(H, W, 0, me, None)
+    ws = _ws(workspace, dev, nbytes)
+    st = lib().rfsr_motion_check(_ptr(cur), _ptr(cur_mask), _ptr(ref_recon), H, W, W,
+                                 ctypes.byref(mc), _ptr(mv), _ptr(acc), _ptr(cost), _ptr(counters),
+                                 _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "rfsr_motion_check")
+    return mv, acc, cost
+
+
+def fsr_blocks(values, cls, fsr: FSRParams | None = None, want_u8=True,
+               workspace: Workspace | None = None, stream=None):
+    """Block-parallel FSR.  Returns (out float32 (H,W), out_u8 uint8 or None)."""
+    fsr = fsr or FSRParams()
+    _plane(values, torch.float32, "values")
+    H, W = values.shape
+    _plane(cls, torch.uint8, "cls", (H, W))
+    if values.stride(0) != cls.stride(0):
+        raise RfsrError("fsr_blocks: values and cls must share the row pitch")
+    pitch = values.stride(0)
+    out = torch.empty_strided((H, W), (pitch, 1), dtype=torch.float32, device=values.device)
+    out_u8 = torch.empty_strided((H, W), (pitch, 1), dtype=torch.uint8, device=values.device) if want_u8 else None
+    fc = fsr.c()
+    ws = _ws(workspace, values.device, workspace_bytes(H, W, 0, None, fsr))
+    st = lib().fsr_blocks(_ptr(values), _ptr(cls), H, W, pitch, ctypes.byref(fc), _ptr(out),
+                          _ptr(out_u8), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "fsr_blocks")
+    return out, out_u8
+
+
+def reconstruct_frame(cur, cur_mask, refs=(), me: MEParams | None = None,
+                      fsr: FSRParams | None = None, out=None, out_u8=None, stage_events=None,
+                      workspace: Workspace | None = None, stream=None):
+    """One recursive frame (Fig. 1 order).  refs: sequence of
+    (recon uint8, meas uint8, mask uint8) device planes for lags 1..len(refs).
+    Returns (out float32 (H,W), out_u8 uint8 (H,W))."""
+    me = me or MEParams()
+    fsr = fsr or FSRParams()
+    _plane(cur, torch.uint8, "cur")
+    H, W = cur.shape
+    _plane(cur_mask, torch.uint8, "cur_mask", (H, W))
+    pitch = cur.stride(0)
+    planes = [cur, cur_mask]
+    nref = len(refs)
+    if nref > 3:
+        raise RfsrError("at most 3 references")
+    for k, (r, m, b) in enumerate(refs):
+        for t, nm in ((r, "recon"), (m, "meas"), (b, "mask")):
+            _plane(t, torch.uint8, f"ref{k}.{nm}", (H, W))
+            planes.append(t)
+    dev = cur.device
+    if out is None:
+        out = torch.empty_strided((H, W), (pitch, 1), dtype=torch.float32, device=dev)
+    if out_u8 is None:
+        out_u8 = torch.empty_strided((H, W), (pitch, 1), dtype=torch.uint8, device=dev)
+    planes += [_plane(out, torch.float32, "out", (H, W)), _plane(out_u8, torch.uint8, "out_u8", (H, W))]
+    if any(p.stride(0) != pitch for p in planes):
+        raise RfsrError("reconstruct_frame: all planes must share the row pitch")
+    arr = ctypes.c_void_p * 3
+    rr = arr(*[r[0].data_ptr() for r in refs])
+    rm = arr(*[r[1].data_ptr() for r in refs])
+    rk = arr(*[r[2].data_ptr() for r in refs])
+    ev = None
+    if stage_events is not None:
+        ev = (ctypes.c_void_p * 4)(*[e.handle for e in stage_events])
+    mc, fc = me.c(), fsr.c()
+    ws = _ws(workspace, dev, workspace_bytes(H, W, nref, me, fsr))
+    st = lib().rfsr_reconstruct_frame(_ptr(cur), _ptr(cur_mask), nref, rr, rm, rk, H, W, pitch,
+                                      ctypes.byref(mc), ctypes.byref(fc), _ptr(out), _ptr(out_u8), ev,
+                                      _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "rfsr_reconstruct_frame")
+    return out, out_u8
+
+
+class Event:
+    """HIP event created by the library (for stage timing)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().rfsr_event_create(ctypes.byref(h)), "rfsr_event_create")
+        self.handle = h.value
+
+    def record(self, stream=None):
+        _check(lib().rfsr_event_record(ctypes.c_void_p(self.handle), _stream(stream)), "rfsr_event_record")
+
+    def elapsed_ms(self, end: "Event") -> float:
+        ms = ctypes.c_float()
+        _check(lib().rfsr_event_elapsed_ms(ctypes.c_void_p(self.handle), ctypes.c_void_p(end.handle),
+                                           ctypes.byref(ms)), "rfsr_event_elapsed_ms")
+        return float(ms.value)
+
+    def __del__(self):
+        try:
+            if self.handle and _lib is not None:
+                _lib.rfsr_event_destroy(ctypes.c_void_p(self.handle))
+        except Exception:
+            pass
+
+
+class Sequence:
+    """Causal recursion over a stream of frames: keeps the last three
+    (reconstruction, measured frame, mask) planes resident on the device and
+    reconstructs each new frame against them (Sec. 2.2, three previous
+    frames as in Sec. 4)."""
+
+    def __init__(self, H, W, me: MEParams | None = None, fsr: FSRParams | None = None,
+                 nref=3, device=None):
+        self.H, self.W = H, W
+        self.me = me or MEParams()
+        self.fsr = fsr or FSRParams()
+        self.nref = nref
+        self.device = device or torch.device("cuda")
+        self.ring = []
+        self.workspace = Workspace(self.device)
+
+    def push(self, meas, mask, stage_events=None, stream=None):
+        refs = [(r[0], r[1], r[2]) for r in reversed(self.ring[-self.nref:])] if self.nref else []
+        out, out_u8 = reconstruct_frame(meas, mask, refs, self.me, self.fsr, stage_events=stage_events,
+                                        workspace=self.workspace, stream=stream)
+        self.ring.append((out_u8, meas, mask))
+        if len(self.ring) > self.nref:
+            self.ring.pop(0)
+        return out, out_u8

@@ -1,0 +1,327 @@
+// Block-parallel frequency selective reconstruction (FSR) for gfx950.
+//
+// Method: Sec. 2.1 (block-wise Fourier-domain model built from the samples of
+// the block and its neighbours), Sec. 3.2 (projected samples take part in the
+// model; the final overwrite uses measured samples only for D-FSR, measured
+// and projected ones for R-FSR), Sec. 4 (concealed weighting 0, so every block
+// is independent).  One 64-lane wavefront owns one 4x4 block and its 32x32
+// support for the whole computation:
+//
+//   1. gather    w = a * rho^dist and w*s on the support            (registers)
+//   2. DFT       Z = DFT2(w*s + i*w): 32-point passes made of one radix-2 step
+//                across the two lane halves and a radix-4x4 16-point FFT in
+//                registers, with a transpose through LDS between the passes
+//   3. split     R = DFT(w*s), W = DFT(w) from Z(k) and Z(-k) (both inputs are
+//                real); R stays in registers (16 bins per lane), W goes to a
+//                32x32 LDS table
+//   4. K greedy iterations: wave argmax of |R_k|^2 (first in row-major order on
+//                ties) with DPP row reductions, dlt = gamma R_b / W0,
+//                R_k -= dlt * W(k - b); the (b, dlt) list goes to LDS
+//   5. synthesis Re sum dlt phi_b on the 16 block pixels, overwrite, store.
+//
+// Precision: everything from the gather to the energies is float64.  CDNA4
+// issues v_fma_f64 at the rate of unpacked float32 FMA, so this costs the
+// extra LDS bytes and registers only.  In float32 the transform alone gives W
+// absolute errors at the scale of w*s (they share one complex FFT), and the
+// argmax then departs from the float64 model in a few blocks per thousand.
+//
+// Register layout during 4: lane l = (h, r) with r = l & 31, h = l >> 5 holds
+// the bins k = (k1, k2) = (j + 16 h, r), j = 0..15, in ascending row-major
+// order along j.  W(k - b) for register j lives in table row
+// ((j - b1) mod 32) xor 16h, column (r - b2) mod 32: the row part is
+// wave-uniform, so each read costs one XOR of a uniform and a per-lane term.
+#include "common.h"
+
+namespace rfsr {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ void dft4(T (&r)[4], T (&i)[4]) {
+    // A_k = sum_j a_j exp(-2 pi i j k / 4)
+    const T t0r = r[0] + r[2], t0i = i[0] + i[2];
+    const T t1r = r[0] - r[2], t1i = i[0] - i[2];
+    const T t2r = r[1] + r[3], t2i = i[1] + i[3];
+    const T t3r = r[1] - r[3], t3i = i[1] - i[3];
+    r[0] = t0r + t2r; i[0] = t0i + t2i;
+    r[2] = t0r - t2r; i[2] = t0i - t2i;
+    r[1] = t1r + t3i; i[1] = t1i - t3r;   // t1 - i t3
+    r[3] = t1r - t3i; i[3] = t1i + t3r;   // t1 + i t3
+}
+
+// In-register forward 16-point DFT, natural order in and out.
+// u = i0 + 4 i1, k = k0 + 4 k1:  U[k] = sum_i0 w4^(i0 k1) w16^(i0 k0) sum_i1 u w4^(i1 k0).
+// tw: exp(-2 pi i t / 32), t = 0..31 (re, im interleaved).
+template <typename T>
+__device__ __forceinline__ void fft16(T (&re)[16], T (&im)[16], const T* __restrict__ tw) {
+    T tr[16], ti[16];
+#pragma unroll
+    for (int i0 = 0; i0 < 4; ++i0) {
+        T ar[4], ai[4];
+#pragma unroll
+        for (int i1 = 0; i1 < 4; ++i1) { ar[i1] = re[i0 + 4 * i1]; ai[i1] = im[i0 + 4 * i1]; }
+        dft4(ar, ai);
+#pragma unroll
+        for (int k0 = 0; k0 < 4; ++k0) {
+            const int e = i0 * k0;   // w16^e = w32^(2e)
+            if (e == 0) {
+                tr[i0 * 4 + k0] = ar[k0]; ti[i0 * 4 + k0] = ai[k0];
+            } else {
+                const T cr = tw[4 * e], ci = tw[4 * e + 1];
+                tr[i0 * 4 + k0] = ar[k0] * cr - ai[k0] * ci;
+                ti[i0 * 4 + k0] = ar[k0] * ci + ai[k0] * cr;
+            }
+        }
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < 4; ++k0) {
+        T br[4], bi[4];
+#pragma unroll
+        for (int i0 = 0; i0 < 4; ++i0) { br[i0] = tr[i0 * 4 + k0]; bi[i0] = ti[i0 * 4 + k0]; }
+        dft4(br, bi);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) { re[k0 + 4 * k1] = br[k1]; im[k0 + 4 * k1] = bi[k1]; }
+    }
+}
+
+// 32-point forward DFT of x[m], m = i + 16 h held by the lane pair (h=0, h=1)
+// at register i.  Afterwards register k' of lane h holds X[2 k' + h].
+template <typename T>
+__device__ __forceinline__ void fft32_pair(T (&re)[16], T (&im)[16], int h, const T* __restrict__ tw) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const T pr = __shfl_xor(re[i], 32);
+        const T pi = __shfl_xor(im[i], 32);
+        // h = 0: x[i] + x[i+16];  h = 1: (x[i] - x[i+16]) * w32^i
+        const T ur = h ? pr - re[i] : re[i] + pr;
+        const T ui = h ? pi - im[i] : im[i] + pi;
+        const T cr = h ? tw[2 * i] : T(1);
+        const T ci = h ? tw[2 * i + 1] : T(0);
+        re[i] = ur * cr - ui * ci;
+        im[i] = ur * ci + ui * cr;
+    }
+    fft16(re, im, tw);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = dpp_u32<CTRL>((uint32_t)u, 0u);
+    const uint32_t hi = dpp_u32<CTRL>((uint32_t)(u >> 32), 0u);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Maximum of non-negative doubles over the 64 lanes (wave-uniform result).
+__device__ __forceinline__ double wave_max_f64(double v) {
+    v = fmax(v, dpp_f64<kDppQuadXor1>(v));
+    v = fmax(v, dpp_f64<kDppQuadXor2>(v));
+    v = fmax(v, dpp_f64<kDppRowHalfMirror>(v));
+    v = fmax(v, dpp_f64<kDppRowMirror>(v));
+    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
+constexpr int kPlane = 33;                       // padded row length of a transpose plane
+
+}  // namespace
+
+__global__ void fsr_tables_kernel(FsrTables* t, double rho) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kSupport * kSupport) {
+        const double dm = (i >> 5) - 15.5, dn = (i & 31) - 15.5;
+        t->rho[i] = pow(rho, sqrt(dm * dm + dn * dn));
+    }
+    if (i < kSupport) {
+        double s, c;
+        sincospi(-2.0 * i / 32.0, &s, &c);
+        t->tw[2 * i] = c;
+        t->tw[2 * i + 1] = s;
+    }
+}
+
+__global__ __launch_bounds__(64) void fsr_block_kernel(
+    const float* __restrict__ values, const uint8_t* __restrict__ cls, int H, int W,
+    int64_t pitch, const FsrTables* __restrict__ tab, float* __restrict__ out,
+    uint8_t* __restrict__ out_u8, int64_t out_pitch, int K, double gamma, double projw,
+    int overwrite) {
+    // W table (32 x 32 complex double); the transpose planes reuse it.  Static,
+    // so its LDS base folds into the read addresses.  The (bin, dlt) list of
+    // K float4 entries is dynamic LDS.
+    __shared__ __align__(16) double2 s_T[32 * 32];
+    __shared__ double s_tw[64];
+    extern __shared__ float4 list[];
+    uint8_t* smem = reinterpret_cast<uint8_t*>(s_T);
+
+    const int nbw = W >> 2;
+    const int nblk = nbw * (H >> 2);
+    const int blk = xcd_remap(blockIdx.x, nblk);
+    const int bi = blk / nbw, bj = blk - bi * nbw;
+    const int lane = threadIdx.x;
+    const int c = lane & 31, h = lane >> 5;
+    const double* __restrict__ tw = tab->tw;
+
+    if (lane < 32) {
+        s_tw[2 * lane] = tw[2 * lane];
+        s_tw[2 * lane + 1] = tw[2 * lane + 1];
+    }
+
+    // 1. gather: lane (h, c) holds support rows m = i + 16 h of column c.
+    double zr[16], zi[16];
+    {
+        const int y0 = 4 * bi - 14, x = 4 * bj - 14 + c;
+        const bool xin = (unsigned)x < (unsigned)W;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = i + 16 * h;
+            const int y = y0 + m;
+            const bool in = xin && (unsigned)y < (unsigned)H;
+            const int64_t off = in ? (int64_t)y * pitch + x : 0;
+            const uint32_t k = in ? (uint32_t)cls[off] : 0u;
+            const bool known = k == 1u || k == 2u;
+            const double a = (k == 1u) ? 1.0 : projw;
+            const double wv = known ? a * tab->rho[m * 32 + c] : 0.0;
+            const double sv = known ? (double)values[off] : 0.0;
+            zr[i] = wv * sv;
+            zi[i] = wv;
+        }
+    }
+
+    // 2. DFT along the support rows m (per column), transpose, DFT along n.
+    double* pl = reinterpret_cast<double*>(smem);   // one 32 x 33 plane at a time
+    fft32_pair(zr, zi, h, tw);                      // register k': Y[k1 = 2k'+h][n = c]
+#pragma unroll
+    for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zr[k];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) zr[i] = pl[c * kPlane + i + 16 * h];   // row k1 = c, n = i + 16h
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zi[k];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) zi[i] = pl[c * kPlane + i + 16 * h];
+    fft32_pair(zr, zi, h, tw);                      // register j: Z[k1 = c][k2 = 2j + h]
+
+    // 3. split Z = DFT(w s) + i DFT(w) using Z(-k), into the iteration layout
+    //    k = (j + 16 h, c).
+    double Rr[16], Ri[16], Wr[16], Wi[16];
+    {
+        const int nc = (32 - c) & 31;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zr[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
+            Wr[j] = pl[k1 * kPlane + c];      // Z.re(k)
+            Wi[j] = pl[nk1 * kPlane + nc];    // Z.re(-k)
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zi[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
+            const double ar = Wr[j], br = Wi[j];                                 // Z.re(k), Z.re(-k)
+            const double ai = pl[k1 * kPlane + c], bim = pl[nk1 * kPlane + nc];  // Z.im(k), Z.im(-k)
+            Rr[j] = 0.5 * (ar + br);
+            Ri[j] = 0.5 * (ai - bim);
+            Wr[j] = 0.5 * (ai + bim);
+            Wi[j] = 0.5 * (br - ar);
+        }
+        __syncthreads();
+    }
+    double2* T = reinterpret_cast<double2*>(smem);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) T[(j + 16 * h) * 32 + c] = make_double2(Wr[j], Wi[j]);
+    const double W0 = readlane_f64(Wr[0], 0);
+    __syncthreads();
+
+    // 4. greedy iterations.
+    const double g = (W0 > 0.0) ? gamma / W0 : 0.0;
+    double lbe = -1.0;
+    int lbj = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const double e = fma(Rr[j], Rr[j], Ri[j] * Ri[j]);
+        if (e > lbe) { lbe = e; lbj = j; }
+    }
+    const uint8_t* Tb = smem;
+    for (int it = 0; it < K; ++it) {
+        const double M = wave_max_f64(lbe);
+        const uint32_t cand = (lbe == M) ? (uint32_t)((lbj + 16 * h) * 32 + c) : 0xFFFFFFFFu;
+        const uint32_t bflat = wave_min_u32(cand);
+        const int b1 = (int)(bflat >> 5), b2 = (int)(bflat & 31);
+        const int owner = b2 + ((b1 >> 4) << 5);
+        const int jb = b1 & 15;
+        const double vr = Rr[jb], vi = Ri[jb];   // jb is wave-uniform: indexed register move
+        const double dr = g * readlane_f64(vr, owner);
+        const double di = g * readlane_f64(vi, owner);
+        if (lane == 0) list[it] = make_float4(__uint_as_float(bflat), (float)dr, (float)di, 0.0f);
+        const uint32_t L = ((uint32_t)h << 13) | ((uint32_t)((c - b2) & 31) << 4);
+        lbe = -1.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t S = (uint32_t)((j - b1) & 31) << 9;   // wave-uniform row part
+            const double2 wv = *reinterpret_cast<const double2*>(Tb + (S ^ L));
+            double xr = fma(-dr, wv.x, Rr[j]);
+            xr = fma(di, wv.y, xr);
+            double xi = fma(-dr, wv.y, Ri[j]);
+            xi = fma(-di, wv.x, xi);
+            Rr[j] = xr;
+            Ri[j] = xi;
+            const double e = fma(xr, xr, xi * xi);
+            if (e > lbe) { lbe = e; lbj = j; }
+        }
+    }
+    __syncthreads();
+
+    // 5. synthesis on the 16 block pixels; four lane groups split the list.
+    const int p = lane & 15, q = lane >> 4;
+    const int pm = 14 + (p >> 2), pn = 14 + (p & 3);
+    double gr = 0.0;
+    for (int it = q; it < K; it += 4) {
+        const float4 e = list[it];
+        const uint32_t bf = __float_as_uint(e.x);
+        const int t = ((int)(bf >> 5) * pm + (int)(bf & 31) * pn) & 31;
+        const double cs = s_tw[2 * t], sn = -s_tw[2 * t + 1];   // exp(+2 pi i t / 32)
+        gr = fma((double)e.y, cs, gr);
+        gr = fma(-(double)e.z, sn, gr);
+    }
+    gr += __shfl_xor(gr, 16);
+    gr += __shfl_xor(gr, 32);
+    if (lane < 16) {
+        const int y = 4 * bi + (p >> 2), x = 4 * bj + (p & 3);
+        const int64_t off = (int64_t)y * pitch + x;
+        const int64_t ooff = (int64_t)y * out_pitch + x;
+        const uint32_t k = cls[off];
+        float o = (float)gr;
+        if (k == 1u || (overwrite == RFSR_RFSR && k == 2u)) o = values[off];
+        out[ooff] = o;
+        if (out_u8) out_u8[ooff] = (uint8_t)rintf(fminf(fmaxf(o, 0.0f), 255.0f));
+    }
+}
+
+hipError_t launch_fsr_tables(FsrTables* t, double rho, hipStream_t s) {
+    hipLaunchKernelGGL(fsr_tables_kernel, dim3(4), dim3(256), 0, s, t, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_fsr(const float* values, const uint8_t* cls, int H, int W, int64_t pitch,
+                      const rfsr_fsr_params& p, const FsrTables* tables, float* out,
+                      uint8_t* out_u8, int64_t out_pitch, hipStream_t s) {
+    const int nblk = (H / kBlock) * (W / kBlock);
+    const size_t shmem = sizeof(float4) * (size_t)p.iters;
+    hipLaunchKernelGGL(fsr_block_kernel, dim3(nblk), dim3(64), shmem, s, values, cls, H, W, pitch,
+                       tables, out, out_u8, out_pitch, p.iters, p.gamma, p.proj_weight, p.overwrite);
+    return hipGetLastError();
+}
+
+}  // namespace rfsr

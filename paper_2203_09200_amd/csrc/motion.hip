@@ -1,0 +1,667 @@
+// Consistency-checked motion path for gfx950: pixel-wise template-matching
+// motion estimation (Sec. 2.2), the reverse checks RME (Sec. 2.2), RMC and
+// FRMC (Sec. 3.1.1), the nearest-neighbour check NNC (Sec. 3.1.2, Eq. (1)),
+// and the projection of measured past pixels (Sec. 2.2).
+//
+// Template: offsets {-1,0,1,2}^2 around p.  Cost of vector v at p:
+//   S(p,v) = sum_d [p+d in frame] b_t(p+d) |f_t(p+d) - Rhat(clamp(p+d+v))|
+// Forward ME takes the minimum of the key (S << 16 | |v|_1 << 10 | raster(v)),
+// a total order equal to (S, |v|_1, raster index of v) for R <= 15.
+// Reverse costs are compared as S/n by exact cross-multiplication.
+#include "common.h"
+
+namespace rfsr {
+
+namespace {
+
+constexpr int kTile = 16;          // forward ME tile: 16 x 16 pixels, 256 threads
+constexpr int kPad = 16;           // border of the window planes
+
+__device__ __forceinline__ bool inside(int y, int x, int H, int W) {
+    return (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
+}
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// ---------------------------------------------------------------------------
+// Forward motion estimation.
+//
+// A workgroup handles a 16x16 pixel tile.  The reference window it needs
+// ((16+3+2R) rows, clamped at the frame edge) is staged in LDS four times,
+// shifted by 0..3 bytes, so that every thread reads its 4-byte aligned row
+// segment with plain dword loads.  Each thread keeps the last four reference
+// rows it needs in registers (one new row per vertical offset) and evaluates
+// four horizontal offsets at once with v_mqsad_pk_u16_u8, which skips the
+// template bytes that are 0: unmeasured template pixels are stored as 0.  A
+// measured pixel of value 0 would be skipped too; waves that contain one add
+// the missing |0 - ref| terms with a second masked SAD against 255.
+template <int R>
+struct MeGeom {
+    static constexpr int NC = 2 * R + 1;            // candidates per axis
+    static constexpr int NG = (NC + 3) / 4;         // groups of four horizontal offsets
+    static constexpr int NV = (NC + 3) / 4 * 4;     // vertical steps, rounded up to 4
+    static constexpr int ROWS = kTile + 2 + NV;     // tile rows incl. template reach and step padding
+    static constexpr int ROWB = kTile + 4 * NG;     // bytes per row of one shifted copy
+    static constexpr int COPY = ROWS * ROWB;        // bytes per shifted copy
+};
+
+// One vertical offset vyi: load the next reference row into r3, evaluate the
+// 2R+1 horizontal offsets against rows (r0, r1, r2, r3), fold into best.
+// key = (S << 16) | (|vx| << 10) + s is minimised first; the per-row part of
+// the tie code, (|vy| << 10) + vyi*(2R+1), is added afterwards (no carry into
+// S since the full code stays below 2^16).  Steps past the last offset
+// (vyi >= 2R+1, from rounding the loop to multiples of 4) only load.
+template <int R, bool BORDER, bool ZFIX>
+__device__ __forceinline__ void me_step(const uint32_t (&r0)[MeGeom<R>::NG + 1],
+                                        const uint32_t (&r1)[MeGeom<R>::NG + 1],
+                                        const uint32_t (&r2)[MeGeom<R>::NG + 1],
+                                        uint32_t (&r3)[MeGeom<R>::NG + 1],
+                                        const uint8_t* __restrict__ rowbase, int ty, int vyi,
+                                        const uint32_t (&t)[4], const uint32_t (&tz)[4],
+                                        uint64_t zfix, int py, int px, int H, int W,
+                                        uint32_t& best) {
+    using G = MeGeom<R>;
+    constexpr int ND = G::NG + 1;
+    {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(rowbase + (ty + vyi + 3) * G::ROWB);
+#pragma unroll
+        for (int k = 0; k < ND; ++k) r3[k] = p[k];
+    }
+    if (vyi >= G::NC) return;
+    const int vy = vyi - R;
+    uint32_t m = 0xFFFFFFFFu;
+#pragma unroll
+    for (int g = 0; g < G::NG; ++g) {
+        uint64_t acc = 0, acc2 = 0;
+        const uint64_t s0 = ((uint64_t)r0[g + 1] << 32) | r0[g];
+        const uint64_t s1 = ((uint64_t)r1[g + 1] << 32) | r1[g];
+        const uint64_t s2 = ((uint64_t)r2[g + 1] << 32) | r2[g];
+        const uint64_t s3 = ((uint64_t)r3[g + 1] << 32) | r3[g];
+        acc = __builtin_amdgcn_mqsad_pk_u16_u8(s0, t[0], acc);
+        acc = __builtin_amdgcn_mqsad_pk_u16_u8(s1, t[1], acc);
+        acc = __builtin_amdgcn_mqsad_pk_u16_u8(s2, t[2], acc);
+        acc = __builtin_amdgcn_mqsad_pk_u16_u8(s3, t[3], acc);
+        if (ZFIX) {
+            acc2 = __builtin_amdgcn_mqsad_pk_u16_u8(s0, tz[0], acc2);
+            acc2 = __builtin_amdgcn_mqsad_pk_u16_u8(s1, tz[1], acc2);
+            acc2 = __builtin_amdgcn_mqsad_pk_u16_u8(s2, tz[2], acc2);
+            acc2 = __builtin_amdgcn_mqsad_pk_u16_u8(s3, tz[3], acc2);
+            acc += zfix - acc2;
+        }
+        const uint32_t lo = (uint32_t)acc, hi = (uint32_t)(acc >> 32);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int s = 4 * g + i;
+            if (s >= G::NC) break;
+            const int vx = s - R;
+            const uint32_t cs = (uint32_t)((vx < 0 ? -vx : vx) << 10) + (uint32_t)s;
+            uint32_t key;
+            if (i == 0) key = (lo << 16) | cs;
+            else if (i == 1) key = (lo & 0xFFFF0000u) | cs;
+            else if (i == 2) key = (hi << 16) | cs;
+            else key = (hi & 0xFFFF0000u) | cs;
+            if (BORDER) {
+                if ((unsigned)(px + vx) >= (unsigned)W) key = 0xFFFFFFFFu;
+            }
+            m = min(m, key);
+        }
+    }
+    const uint32_t cvy = (uint32_t)((vy < 0 ? -vy : vy) << 10) + (uint32_t)(vyi * G::NC);
+    bool ok = m != 0xFFFFFFFFu;
+    if (BORDER) ok = ok && (unsigned)(py + vy) < (unsigned)H;
+    if (ok) best = min(best, m + cvy);
+}
+
+template <int R, bool BORDER, bool ZFIX>
+__device__ __forceinline__ uint32_t me_search(const uint8_t* __restrict__ rowbase, int ty,
+                                              const uint32_t (&t)[4], const uint32_t (&tz)[4],
+                                              uint32_t nz, int py, int px, int H, int W) {
+    using G = MeGeom<R>;
+    constexpr int ND = G::NG + 1;
+    uint32_t a[ND], b[ND], c[ND], d[ND];
+    {
+        const uint32_t* p0 = reinterpret_cast<const uint32_t*>(rowbase + (ty + 0) * G::ROWB);
+        const uint32_t* p1 = reinterpret_cast<const uint32_t*>(rowbase + (ty + 1) * G::ROWB);
+        const uint32_t* p2 = reinterpret_cast<const uint32_t*>(rowbase + (ty + 2) * G::ROWB);
+#pragma unroll
+        for (int k = 0; k < ND; ++k) { a[k] = p0[k]; b[k] = p1[k]; c[k] = p2[k]; }
+    }
+    const uint64_t zfix = (uint64_t)(nz * 255u) * 0x0001000100010001ull;
+    uint32_t best = 0xFFFFFFFFu;
+#pragma unroll 1
+    for (int v0 = 0; v0 < G::NC; v0 += 4) {
+        me_step<R, BORDER, ZFIX>(a, b, c, d, rowbase, ty, v0 + 0, t, tz, zfix, py, px, H, W, best);
+        me_step<R, BORDER, ZFIX>(b, c, d, a, rowbase, ty, v0 + 1, t, tz, zfix, py, px, H, W, best);
+        me_step<R, BORDER, ZFIX>(c, d, a, b, rowbase, ty, v0 + 2, t, tz, zfix, py, px, H, W, best);
+        me_step<R, BORDER, ZFIX>(d, a, b, c, rowbase, ty, v0 + 3, t, tz, zfix, py, px, H, W, best);
+    }
+    return best;
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void me_forward_kernel(
+    const uint8_t* __restrict__ cur, const uint8_t* __restrict__ mask,
+    const uint8_t* __restrict__ ref, int H, int W, int64_t pitch, int8_t* __restrict__ mv_a,
+    int8_t* __restrict__ mv_b, int64_t mv_pitch, uint16_t* __restrict__ cost, int64_t cost_pitch,
+    uint8_t* __restrict__ nmap, unsigned long long* __restrict__ counters) {
+    using G = MeGeom<R>;
+    __shared__ __align__(16) uint8_t s_ref[4 * G::COPY];
+
+    const int tiles_x = (W + kTile - 1) / kTile;
+    const int ntiles = tiles_x * ((H + kTile - 1) / kTile);
+    const int tile = xcd_remap(blockIdx.x, ntiles);
+    const int y0 = (tile / tiles_x) * kTile, x0 = (tile % tiles_x) * kTile;
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+
+    // Stage the four shifted copies of the clamped reference window.
+    {
+        constexpr int DW = G::ROWB / 4;        // dwords per copy row
+        constexpr int TOTAL = 4 * G::ROWS * DW;
+        const int gy0 = y0 - 1 - R, gx0 = x0 - 1 - R;
+        for (int e = tid; e < TOTAL; e += 256) {
+            const int a = e / (G::ROWS * DW);
+            const int rem = e - a * (G::ROWS * DW);
+            const int tr = rem / DW, kd = rem - tr * DW;
+            const int64_t rowoff = (int64_t)clampi(gy0 + tr, 0, H - 1) * pitch;
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int gx = clampi(gx0 + 4 * kd + b + a, 0, W - 1);
+                v |= (uint32_t)ref[rowoff + gx] << (8 * b);
+            }
+            reinterpret_cast<uint32_t*>(s_ref + a * G::COPY + tr * G::ROWB)[kd] = v;
+        }
+    }
+
+    // Template of the current frame: measured bytes, 0 where unmeasured.
+    const int py = y0 + ty, px = x0 + tx;
+    uint32_t t[4], tz[4];
+    uint32_t n = 0, nz = 0;
+#pragma unroll
+    for (int dy = 0; dy < 4; ++dy) {
+        uint32_t tv = 0, zv = 0;
+        const int y = py - 1 + dy;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = px - 1 + i;
+            if (inside(y, x, H, W)) {
+                const int64_t off = (int64_t)y * pitch + x;
+                if (mask[off]) {
+                    const uint32_t v = cur[off];
+                    tv |= v << (8 * i);
+                    zv |= (v == 0 ? 0xFFu : 0u) << (8 * i);
+                    n += 1;
+                    nz += (v == 0);
+                }
+            }
+        }
+        t[dy] = tv;
+        tz[dy] = zv;
+    }
+    __syncthreads();
+
+    const bool interior = (y0 - R >= 0) && (y0 + kTile - 1 + R <= H - 1) && (x0 - R >= 0) &&
+                          (x0 + kTile - 1 + R <= W - 1);
+    const bool anyz = __any(nz != 0);
+    const uint8_t* rowbase = s_ref + (tx & 3) * G::COPY + 4 * (tx >> 2);
+    uint32_t best;
+    if (interior) {
+        best = anyz ? me_search<R, false, true>(rowbase, ty, t, tz, nz, py, px, H, W)
+                    : me_search<R, false, false>(rowbase, ty, t, tz, nz, py, px, H, W);
+    } else {
+        best = anyz ? me_search<R, true, true>(rowbase, ty, t, tz, nz, py, px, H, W)
+                    : me_search<R, true, false>(rowbase, ty, t, tz, nz, py, px, H, W);
+    }
+
+    const bool valid = py < H && px < W;
+    if (valid) {
+        const int raster = (int)(best & 0x3FFu);
+        const int vyi = raster / G::NC, s = raster - vyi * G::NC;
+        mv_a[(int64_t)py * mv_pitch + px] = (int8_t)(vyi - R);
+        mv_b[(int64_t)py * mv_pitch + px] = (int8_t)(s - R);
+        if (cost) cost[(int64_t)py * cost_pitch + px] = (uint16_t)(best >> 16);
+        if (nmap) nmap[(int64_t)py * W + px] = (uint8_t)n;
+    }
+    if (counters) {
+        unsigned long long cnt = 0;
+        if (valid) {
+            const int ny = min(R, py) + min(R, H - 1 - py) + 1;
+            const int nx = min(R, px) + min(R, W - 1 - px) + 1;
+            cnt = (unsigned long long)(ny * nx);
+        }
+        cnt = wave_sum_u64(cnt);
+        if ((tid & 63) == 0) atomicAdd(counters + RFSR_CNT_FORWARD_COSTS, cnt);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Window planes for the reverse costs.  Entry (y, x) of the padded plane
+// (rows -kPad..H+kPad-1, columns -kPad..W+kPad-1) holds, for the template row
+// starting at column x-1: .x = the measured bytes of f_t (0 unmeasured or
+// outside), .y = 0xFF per byte where a measurement exists.
+__global__ void windows_kernel(const uint8_t* __restrict__ cur, const uint8_t* __restrict__ mask,
+                               int H, int W, int64_t pitch, uint2* __restrict__ fm) {
+    const int Wp = W + 2 * kPad, Hp = H + 2 * kPad;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Wp * Hp) return;
+    const int y = e / Wp - kPad, x = e % Wp - kPad;
+    uint32_t f = 0, m = 0;
+    if ((unsigned)y < (unsigned)H) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int xx = x - 1 + i;
+            if ((unsigned)xx < (unsigned)W) {
+                const int64_t off = (int64_t)y * pitch + xx;
+                if (mask[off]) {
+                    f |= (uint32_t)cur[off] << (8 * i);
+                    m |= 0xFFu << (8 * i);
+                }
+            }
+        }
+    }
+    fm[e] = make_uint2(f, m);
+}
+
+struct RevCtx {
+    const uint2* fm;   // padded window plane, origin at (kPad, kPad)
+    int Wp;
+    const uint8_t* nmap;
+    int H, W;
+};
+
+// Reverse template cost: template r (4 rows of reference bytes at q) against
+// the measured pixels of the current frame around s: S and its n.
+__device__ __forceinline__ uint32_t rev_cost(const RevCtx& c, const uint32_t (&r)[4], int sy, int sx) {
+    const uint2* p = c.fm + (int64_t)(sy - 1 + kPad) * c.Wp + (sx + kPad);
+    uint32_t S = 0;
+#pragma unroll
+    for (int dy = 0; dy < 4; ++dy) {
+        const uint2 v = p[dy * c.Wp];
+        S = __builtin_amdgcn_sad_u8(v.x, r[dy] & v.y, S);
+    }
+    return S;
+}
+
+__device__ __forceinline__ void ref_template(const uint8_t* __restrict__ ref, int H, int W,
+                                             int64_t pitch, int qy, int qx, uint32_t (&r)[4]) {
+#pragma unroll
+    for (int dy = 0; dy < 4; ++dy) {
+        const int64_t rowoff = (int64_t)clampi(qy - 1 + dy, 0, H - 1) * pitch;
+        uint32_t v = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v |= (uint32_t)ref[rowoff + clampi(qx - 1 + i, 0, W - 1)] << (8 * i);
+        r[dy] = v;
+    }
+}
+
+// Reverse motion field for RME: for every q the minimiser of
+// (S_rev/n_rev, |u|_1, raster(u)) over u in [-R,R]^2 with q+u in the frame.
+__global__ __launch_bounds__(256) void reverse_me_kernel(
+    RevCtx c, const uint8_t* __restrict__ ref, int64_t pitch, int R, int8_t* __restrict__ ra,
+    int8_t* __restrict__ rb, unsigned long long* __restrict__ counters) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = e < c.H * c.W;
+    unsigned long long evals = 0;
+    if (valid) {
+        const int qy = e / c.W, qx = e - qy * c.W;
+        uint32_t r[4];
+        ref_template(ref, c.H, c.W, pitch, qy, qx, r);
+        uint32_t bS = 0, bn = 1, bl1 = 0;
+        int bu = 0, bv = 0;
+        bool has = false;
+        for (int uy = -R; uy <= R; ++uy) {
+            const int sy = qy + uy;
+            if ((unsigned)sy >= (unsigned)c.H) continue;
+            for (int ux = -R; ux <= R; ++ux) {
+                const int sx = qx + ux;
+                if ((unsigned)sx >= (unsigned)c.W) continue;
+                const uint32_t S = rev_cost(c, r, sy, sx);
+                const uint32_t n = c.nmap[(int64_t)sy * c.W + sx];
+                const uint32_t l1 = (uint32_t)(abs(uy) + abs(ux));
+                const uint32_t lhs = S * bn, rhs = bS * n;
+                ++evals;
+                if (!has || lhs < rhs || (lhs == rhs && l1 < bl1)) {
+                    has = true; bS = S; bn = n; bl1 = l1; bu = uy; bv = ux;
+                }
+            }
+        }
+        ra[e] = (int8_t)bu;
+        rb[e] = (int8_t)bv;
+    }
+    if (counters) {
+        evals = wave_sum_u64(evals);
+        if ((threadIdx.x & 63) == 0) atomicAdd(counters + RFSR_CNT_CHECK_COSTS, evals);
+    }
+}
+
+struct AcceptIO {
+    const int8_t* mv_a;
+    const int8_t* mv_b;
+    int64_t mv_pitch;
+    uint8_t* accept;
+    int64_t acc_pitch;
+    const uint8_t* cur_mask;   // with ref_mask: restrict to projectable pixels
+    const uint8_t* ref_mask;
+    int64_t pitch;
+};
+
+__global__ void rme_accept_kernel(AcceptIO io, int H, int W, const int8_t* __restrict__ ra,
+                                  const int8_t* __restrict__ rb, unsigned long long* counters) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long acc_cnt = 0;
+    if (e < H * W) {
+        const int y = e / W, x = e - y * W;
+        const int a = io.mv_a[(int64_t)y * io.mv_pitch + x], b = io.mv_b[(int64_t)y * io.mv_pitch + x];
+        const int q = (y + a) * W + (x + b);
+        const bool ok = ra[q] == -a && rb[q] == -b;
+        io.accept[(int64_t)y * io.acc_pitch + x] = ok;
+        acc_cnt = ok;
+    }
+    if (counters) {
+        acc_cnt = wave_sum_u64(acc_cnt);
+        if ((threadIdx.x & 63) == 0) atomicAdd(counters + RFSR_CNT_ACCEPTED, acc_cnt);
+    }
+}
+
+// RMC (DENSE, offsets [-rr, rr]^2) and FRMC ({-7,-3,-1,0,1,3,7}^2): accept
+// iff S(p,v)/n(p) < S(p+d, v-d)/n(p+d) for every red d with p+d in the frame.
+// Reds are tried in raster order and the test stops at the first loser.
+// CASCADE: only pixels already accepted (by NNC) are tested, the rest stay 0.
+template <bool DENSE, bool CASCADE>
+__global__ __launch_bounds__(256) void rmc_kernel(
+    RevCtx c, AcceptIO io, const uint8_t* __restrict__ ref, const uint16_t* __restrict__ cost,
+    int64_t cost_pitch, int rr, unsigned long long* __restrict__ counters) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long evals = 0, checked = 0, accepted = 0;
+    if (e < c.H * c.W) {
+        const int py = e / c.W, px = e - py * c.W;
+        bool ok = true;
+        if (CASCADE) ok = io.accept[(int64_t)py * io.acc_pitch + px] != 0;
+        const int a = io.mv_a[(int64_t)py * io.mv_pitch + px];
+        const int b = io.mv_b[(int64_t)py * io.mv_pitch + px];
+        if (ok && io.ref_mask) {
+            // Only projectable pixels matter: missing now, measured at p+v.
+            ok = io.cur_mask[(int64_t)py * io.pitch + px] == 0 &&
+                 io.ref_mask[(int64_t)(py + a) * io.pitch + (px + b)] != 0;
+        }
+        if (ok) {
+            checked = 1;
+            uint32_t r[4];
+            ref_template(ref, c.H, c.W, io.pitch, py + a, px + b, r);
+            const uint32_t Sg = cost[(int64_t)py * cost_pitch + px];
+            const uint32_t ng = c.nmap[(int64_t)py * c.W + px];
+            // FRMC offsets {-7,-3,-1,0,1,3,7}: sign(i-3) * (2^|i-3| - 1)
+            const int n1 = DENSE ? 2 * rr + 1 : 7;
+            for (int iy = 0; iy < n1 && ok; ++iy) {
+                const int dy = DENSE ? iy - rr : (iy < 3 ? -1 : 1) * ((1 << abs(iy - 3)) - 1);
+                const int sy = py + dy;
+                if ((unsigned)sy >= (unsigned)c.H) continue;
+                for (int ix = 0; ix < n1; ++ix) {
+                    const int dx = DENSE ? ix - rr : (ix < 3 ? -1 : 1) * ((1 << abs(ix - 3)) - 1);
+                    const int sx = px + dx;
+                    if ((dy | dx) == 0 || (unsigned)sx >= (unsigned)c.W) continue;
+                    const uint32_t S = rev_cost(c, r, sy, sx);
+                    const uint32_t n = c.nmap[(int64_t)sy * c.W + sx];
+                    ++evals;
+                    if (S * ng <= Sg * n) { ok = false; break; }
+                }
+            }
+        }
+        io.accept[(int64_t)py * io.acc_pitch + px] = ok;
+        accepted = ok;
+    }
+    if (counters) {
+        evals = wave_sum_u64(evals);
+        checked = wave_sum_u64(checked);
+        accepted = wave_sum_u64(accepted);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(counters + RFSR_CNT_CHECK_COSTS, evals);
+            atomicAdd(counters + RFSR_CNT_CHECKED_PIXELS, checked);
+            atomicAdd(counters + RFSR_CNT_ACCEPTED, accepted);
+        }
+    }
+}
+
+// ----------------------------------------------------------------- NNC ----
+__device__ __forceinline__ void sort2(int& a, int& b) {
+    const int lo = min(a, b), hi = max(a, b);
+    a = lo; b = hi;
+}
+__device__ __forceinline__ int med3(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
+
+// Median of a 3x3 neighbourhood: sort each row, then the median of
+// (largest row minimum, median of row medians, smallest row maximum).
+__device__ __forceinline__ int median9(int (&v)[9]) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        sort2(v[3 * r], v[3 * r + 1]);
+        sort2(v[3 * r + 1], v[3 * r + 2]);
+        sort2(v[3 * r], v[3 * r + 1]);
+    }
+    const int lo = max(max(v[0], v[3]), v[6]);
+    const int hi = min(min(v[2], v[5]), v[8]);
+    const int md = med3(v[1], v[4], v[7]);
+    return med3(lo, md, hi);
+}
+
+__global__ void median_kernel(const int8_t* __restrict__ a, const int8_t* __restrict__ b,
+                              int64_t mv_pitch, int H, int W, int8_t* __restrict__ ma,
+                              int8_t* __restrict__ mb) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= H * W) return;
+    const int y = e / W, x = e - y * W;
+    int va[9], vb[9];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+        const int64_t ro = (int64_t)clampi(y - 1 + dy, 0, H - 1) * mv_pitch;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int xx = clampi(x - 1 + dx, 0, W - 1);
+            va[3 * dy + dx] = a[ro + xx];
+            vb[3 * dy + dx] = b[ro + xx];
+        }
+    }
+    ma[e] = (int8_t)median9(va);
+    mb[e] = (int8_t)median9(vb);
+}
+
+__global__ void nnc_kernel(const int8_t* __restrict__ ma, const int8_t* __restrict__ mb, int H,
+                           int W, uint8_t* __restrict__ accept, int64_t acc_pitch,
+                           unsigned long long* counters, bool count) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long acc_cnt = 0;
+    if (e < H * W) {
+        const int y = e / W, x = e - y * W;
+        const int a = ma[e], b = mb[e];
+        bool ok = true;
+        if (y > 0) ok &= abs(a - ma[e - W]) + abs(b - mb[e - W]) <= 1;
+        if (y < H - 1) ok &= abs(a - ma[e + W]) + abs(b - mb[e + W]) <= 1;
+        if (x > 0) ok &= abs(a - ma[e - 1]) + abs(b - mb[e - 1]) <= 1;
+        if (x < W - 1) ok &= abs(a - ma[e + 1]) + abs(b - mb[e + 1]) <= 1;
+        accept[(int64_t)y * acc_pitch + x] = ok;
+        acc_cnt = ok;
+    }
+    if (count && counters) {
+        acc_cnt = wave_sum_u64(acc_cnt);
+        if ((threadIdx.x & 63) == 0) atomicAdd(counters + RFSR_CNT_ACCEPTED, acc_cnt);
+    }
+}
+
+__global__ void accept_all_kernel(uint8_t* __restrict__ accept, int64_t acc_pitch, int H, int W,
+                                  unsigned long long* counters) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < H * W) accept[(int64_t)(e / W) * acc_pitch + (e % W)] = 1;
+    if (counters && blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd(counters + RFSR_CNT_ACCEPTED, (unsigned long long)H * W);
+}
+
+// ----------------------------------------------------------- projection ----
+struct ProjArgs {
+    ProjRef r[3];
+};
+
+__global__ void project_kernel(const uint8_t* __restrict__ cur, const uint8_t* __restrict__ cur_mask,
+                               int H, int W, int64_t pitch, int nref, ProjArgs pa, int64_t ipitch,
+                               float* __restrict__ values, uint8_t* __restrict__ cls) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= H * W) return;
+    const int y = e / W, x = e - y * W;
+    const int64_t off = (int64_t)y * pitch + x;
+    if (cur_mask[off]) {
+        values[e] = (float)cur[off];
+        cls[e] = 1;
+        return;
+    }
+    uint32_t total = 0, count = 0;
+    for (int k = 0; k < nref; ++k) {
+        const ProjRef& r = pa.r[k];
+        const int64_t io = (int64_t)y * ipitch + x;
+        if (!r.accept[io]) continue;
+        const int qy = y + r.mv_a[io], qx = x + r.mv_b[io];
+        const int64_t qo = (int64_t)qy * pitch + qx;
+        if (r.mask[qo]) {
+            total += r.meas[qo];
+            count += 1;
+        }
+    }
+    values[e] = count ? (float)total / (float)count : 0.0f;
+    cls[e] = count ? 2 : 0;
+}
+
+// ------------------------------------------------------------- dispatch ----
+template <int R>
+hipError_t launch_me_r(const uint8_t* cur, const uint8_t* mask, const uint8_t* ref, int H, int W,
+                       int64_t pitch, int8_t* a, int8_t* b, int64_t mvp, uint16_t* cost,
+                       int64_t cp, uint8_t* nmap, unsigned long long* counters, hipStream_t s) {
+    const int nt = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+    hipLaunchKernelGGL(me_forward_kernel<R>, dim3(nt), dim3(256), 0, s, cur, mask, ref, H, W, pitch,
+                       a, b, mvp, cost, cp, nmap, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_me(int R, const uint8_t* cur, const uint8_t* mask, const uint8_t* ref, int H,
+                     int W, int64_t pitch, int8_t* a, int8_t* b, int64_t mvp, uint16_t* cost,
+                     int64_t cp, uint8_t* nmap, unsigned long long* counters, hipStream_t s) {
+#define RFSR_ME_CASE(r) \
+    case r: return launch_me_r<r>(cur, mask, ref, H, W, pitch, a, b, mvp, cost, cp, nmap, counters, s);
+    switch (R) {
+        RFSR_ME_CASE(0) RFSR_ME_CASE(1) RFSR_ME_CASE(2) RFSR_ME_CASE(3) RFSR_ME_CASE(4)
+        RFSR_ME_CASE(5) RFSR_ME_CASE(6) RFSR_ME_CASE(7) RFSR_ME_CASE(8) RFSR_ME_CASE(9)
+        RFSR_ME_CASE(10) RFSR_ME_CASE(11) RFSR_ME_CASE(12) RFSR_ME_CASE(13) RFSR_ME_CASE(14)
+        RFSR_ME_CASE(15)
+        default: return hipErrorInvalidValue;
+    }
+#undef RFSR_ME_CASE
+}
+
+inline unsigned grid1(int n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// Workspace of run_motion_check: nmap, window plane, reverse field, medians,
+// green cost (when the caller passes none).
+struct MotionLayout {
+    size_t nmap, fm, ra, rb, ma, mb, cost, total;
+    MotionLayout(int H, int W) {
+        const size_t px = (size_t)H * W;
+        size_t o = 0;
+        nmap = o; o = align256(o + px);
+        fm = o; o = align256(o + sizeof(uint2) * (size_t)(H + 2 * kPad) * (W + 2 * kPad));
+        ra = o; o = align256(o + px);
+        rb = o; o = align256(o + px);
+        ma = o; o = align256(o + px);
+        mb = o; o = align256(o + px);
+        cost = o; o = align256(o + 2 * px);
+        total = o;
+    }
+};
+
+size_t motion_ws_bytes(int H, int W, const rfsr_me_params&) { return MotionLayout(H, W).total; }
+
+hipError_t run_motion_check(const uint8_t* cur, const uint8_t* cur_mask, const uint8_t* ref, int H,
+                            int W, int64_t pitch, const rfsr_me_params& me, int8_t* mv_a,
+                            int8_t* mv_b, int64_t mv_pitch, uint8_t* accept, int64_t acc_pitch,
+                            uint16_t* cost, int64_t cost_pitch, unsigned long long* counters,
+                            void* ws, bool windows_ready, const uint8_t* ref_mask_for_need,
+                            hipStream_t s) {
+    const MotionLayout L(H, W);
+    uint8_t* base = static_cast<uint8_t*>(ws);
+    uint8_t* nmap = base + L.nmap;
+    uint2* fm = reinterpret_cast<uint2*>(base + L.fm);
+    if (!cost) {
+        cost = reinterpret_cast<uint16_t*>(base + L.cost);
+        cost_pitch = W;
+    }
+    hipError_t err = launch_me(me.search, cur, cur_mask, ref, H, W, pitch, mv_a, mv_b, mv_pitch, cost,
+                               cost_pitch, nmap, counters, s);
+    if (err != hipSuccess) return err;
+
+    const int npx = H * W;
+    const int check = me.check;
+    const bool need_windows = check == RFSR_CHECK_RME || check == RFSR_CHECK_RMC ||
+                              check == RFSR_CHECK_FRMC || check == RFSR_CHECK_NNC_FRMC;
+    if (need_windows && !windows_ready) {
+        const int nfm = (H + 2 * kPad) * (W + 2 * kPad);
+        hipLaunchKernelGGL(windows_kernel, dim3(grid1(nfm)), dim3(256), 0, s, cur, cur_mask, H, W, pitch, fm);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
+    RevCtx rc{fm, W + 2 * kPad, nmap, H, W};
+    AcceptIO io{mv_a, mv_b, mv_pitch, accept, acc_pitch,
+                ref_mask_for_need ? cur_mask : nullptr, ref_mask_for_need, pitch};
+    const int rr = me.rmc_radius > 0 ? me.rmc_radius : me.search;
+    switch (check) {
+        case RFSR_CHECK_NONE:
+            hipLaunchKernelGGL(accept_all_kernel, dim3(grid1(npx)), dim3(256), 0, s, accept, acc_pitch, H, W,
+                               counters);
+            break;
+        case RFSR_CHECK_RME: {
+            int8_t* ra = reinterpret_cast<int8_t*>(base + L.ra);
+            int8_t* rb = reinterpret_cast<int8_t*>(base + L.rb);
+            hipLaunchKernelGGL(reverse_me_kernel, dim3(grid1(npx)), dim3(256), 0, s, rc, ref, pitch,
+                               me.search, ra, rb, counters);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+            hipLaunchKernelGGL(rme_accept_kernel, dim3(grid1(npx)), dim3(256), 0, s, io, H, W, ra, rb,
+                               counters);
+            break;
+        }
+        case RFSR_CHECK_RMC:
+            hipLaunchKernelGGL((rmc_kernel<true, false>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref,
+                               cost, cost_pitch, rr, counters);
+            break;
+        case RFSR_CHECK_FRMC:
+            hipLaunchKernelGGL((rmc_kernel<false, false>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref,
+                               cost, cost_pitch, rr, counters);
+            break;
+        case RFSR_CHECK_NNC:
+        case RFSR_CHECK_NNC_FRMC: {
+            int8_t* ma = reinterpret_cast<int8_t*>(base + L.ma);
+            int8_t* mb = reinterpret_cast<int8_t*>(base + L.mb);
+            hipLaunchKernelGGL(median_kernel, dim3(grid1(npx)), dim3(256), 0, s, mv_a, mv_b, mv_pitch, H, W,
+                               ma, mb);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+            hipLaunchKernelGGL(nnc_kernel, dim3(grid1(npx)), dim3(256), 0, s, ma, mb, H, W, accept, acc_pitch,
+                               counters, check == RFSR_CHECK_NNC);
+            if (check == RFSR_CHECK_NNC_FRMC) {
+                if ((err = hipGetLastError()) != hipSuccess) return err;
+                hipLaunchKernelGGL((rmc_kernel<false, true>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref,
+                                   cost, cost_pitch, rr, counters);
+            }
+            break;
+        }
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const uint8_t* cur, const uint8_t* cur_mask, int H, int W, int64_t pitch,
+                          int nref, const ProjRef* refs, int64_t ipitch, float* values, uint8_t* cls,
+                          hipStream_t s) {
+    ProjArgs pa{};
+    for (int k = 0; k < nref && k < 3; ++k) pa.r[k] = refs[k];
+    hipLaunchKernelGGL(project_kernel, dim3(grid1(H * W)), dim3(256), 0, s, cur, cur_mask, H, W, pitch,
+                       nref, pa, ipitch, values, cls);
+    return hipGetLastError();
+}
+
+}  // namespace rfsr

@@ -81,14 +81,16 @@ def mask_sequence(kind: str, n: int, h: int, w: int, rng: np.random.Generator) -
 
 def bandlimited_noise(h: int, w: int, sigma: float, rng: np.random.Generator) -> np.ndarray:
     """White N(0,1) noise low-pass filtered by a Gaussian transfer function
-    of spatial std `sigma` pixels (periodic), normalised to unit std."""
+    of spatial std `sigma` pixels (periodic), scaled to unit expected
+    variance (the filter's mean squared gain), so that fields much smoother
+    than the canvas stay smooth instead of being blown up."""
     z = rng.standard_normal((h, w))
     fy = np.fft.fftfreq(h)[:, None]
     fx = np.fft.rfftfreq(w)[None, :]
     tf = np.exp(-2.0 * (np.pi * sigma) ** 2 * (fy ** 2 + fx ** 2))
     out = np.fft.irfft2(np.fft.rfft2(z) * tf, s=(h, w))
-    sd = out.std()
-    return out / sd if sd > 0 else out
+    full = np.exp(-2.0 * (np.pi * sigma) ** 2 * (fy ** 2 + np.fft.fftfreq(w)[None, :] ** 2))
+    return out / np.sqrt(np.mean(full ** 2))
 
 
 def _to_u8(x: np.ndarray) -> np.ndarray:

@@ -1,0 +1,80 @@
+"""GPU parity of rfsr_reconstruct_frame (Fig. 1 order: ME, check,
+projection, FSR, overwrite, quantisation) and of the causal recursion."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from _gpu import FSR_TOL, PSNR_TOL, compare_fsr, dev, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite="dfsr"):
+    R = need_gpu()
+    rng = np.random.default_rng(seed)
+    frames, _ = synth.video_translate_edges(nref + 1, H, W, rng, max_step=3, n_edges=3)
+    masks = synth.mask_sequence(kind, nref + 1, H, W, rng)
+    meas = synth.measured(frames, masks)
+    t = nref
+    # both sides consume the same uint8 references (true frames, lightly perturbed)
+    recon = [np.clip(frames[t - 1 - k].astype(int) + rng.integers(-3, 4, (H, W)), 0, 255).astype(np.uint8)
+             for k in range(nref)]
+    refs = [(recon[k], meas[t - 1 - k], masks[t - 1 - k]) for k in range(nref)]
+    me = O.MEParams(search=search, check=check)
+    fsr = O.FSRParams(iters=K, overwrite=overwrite)
+    ora = O.reconstruct_frame(meas[t], masks[t], refs, me, fsr)
+    out, out_u8 = R.reconstruct_frame(dev(meas[t]), dev(masks[t]),
+                                      [(dev(r), dev(mm), dev(b)) for r, mm, b in refs],
+                                      R.MEParams(search=search, check=check),
+                                      R.FSRParams(iters=K, overwrite=overwrite))
+    out, out_u8 = host(out), host(out_u8)
+    worst, namb, nb = compare_fsr(out, ora["out"], ora["gaps"])
+    print(f"frame {H}x{W} {check} {kind} nref={nref}: max {worst:.2e}, ambiguous {namb}/{nb}, "
+          f"projected {(ora['cls'] == 2).mean():.3f}")
+    assert worst <= FSR_TOL
+    assert namb <= 0.05 * nb
+    assert abs(O.psnr(frames[t], out, 8) - O.psnr(frames[t], ora["out"], 8)) <= PSNR_TOL
+    assert (out_u8 == O.quantize(out)).all()
+    return ora
+
+
+@pytest.mark.parametrize("check,kind,nref", [("nnc_frmc", "dynamic", 3), ("rme", "fixed", 2),
+                                             ("rmc", "dynamic", 1), ("none", "dynamic", 3),
+                                             ("frmc", "fixed", 3), ("nnc", "dynamic", 2)])
+def test_frame_teacher_forced(check, kind, nref):
+    teacher_forced_case(64, 80, check, kind, nref, seed=10 + nref)
+
+
+def test_frame_rfsr_overwrite():
+    teacher_forced_case(64, 64, "nnc_frmc", "dynamic", 3, seed=3, overwrite="rfsr")
+
+
+def test_frame_no_reference_is_single_frame_fsr():
+    R = need_gpu()
+    f, m = synth.workload_c2(n=1, h=64, w=64, seed=2)
+    meas = synth.measured(f, m)[0]
+    out, _ = R.reconstruct_frame(dev(meas), dev(m[0]), [], R.MEParams(), R.FSRParams(iters=40))
+    out2, _ = R.fsr_blocks(dev(meas.astype(np.float32)), dev(m[0]), R.FSRParams(iters=40))
+    assert np.array_equal(host(out), host(out2))
+
+
+def test_sequence_free_running_psnr():
+    """Free-running recursion (each side consumes its own reconstructions):
+    per-frame PSNR within 0.01 dB of the oracle's recursion."""
+    R = need_gpu()
+    rng = np.random.default_rng(21)
+    H = W = 64
+    frames, _ = synth.video_translate_edges(5, H, W, rng, max_step=2, n_edges=2)
+    masks = synth.mask_sequence("dynamic", 5, H, W, rng)
+    meas = synth.measured(frames, masks)
+    me, fsr = O.MEParams(search=5, check="nnc_frmc"), O.FSRParams(iters=40)
+    ora = O.reconstruct_sequence(meas, masks, me, fsr)
+    seq = R.Sequence(H, W, R.MEParams(search=5, check="nnc_frmc"), R.FSRParams(iters=40))
+    for t in range(5):
+        out, _ = seq.push(dev(meas[t]), dev(masks[t]))
+        p_g = O.psnr(frames[t], host(out), 8)
+        p_o = O.psnr(frames[t], ora[t]["out"], 8)
+        print(f"t={t}: gpu {p_g:.4f} dB oracle {p_o:.4f} dB")
+        assert abs(p_g - p_o) <= PSNR_TOL

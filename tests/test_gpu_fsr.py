@@ -1,0 +1,129 @@
+"""GPU parity of fsr_blocks (block-parallel FSR, Sec. 2.1 / 3.2) against the
+float64 oracle: max-abs 1e-3 on the 0..255 scale outside tie-ambiguous
+blocks, frame PSNR within 0.01 dB, plus closed forms, invariances and edge
+cases.  Every call goes through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from _gpu import FSR_TOL, PSNR_TOL, compare_fsr, dev, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def run_gpu(R, values, cls, K=100, overwrite="dfsr", rho=0.7, gamma=0.5, pw=1.0):
+    out, out_u8 = R.fsr_blocks(dev(values, torch.float32), dev(cls),
+                               R.FSRParams(iters=K, overwrite=overwrite, rho=rho, gamma=gamma,
+                                           proj_weight=pw))
+    return host(out), host(out_u8)
+
+
+def frame(seed, H, W, kind="dynamic"):
+    f, m = synth.workload_c2(n=1, h=H, w=W, seed=seed) if kind == "dynamic" else synth.workload_c1(seed=seed)
+    if kind != "dynamic":
+        f, m = f[:1, :H, :W], m[:1, :H, :W]
+    return f[0], m[0], synth.measured(f, m)[0]
+
+
+@pytest.mark.parametrize("H,W,kind,K", [(128, 128, "dynamic", 100), (128, 128, "fixed", 100),
+                                        (132, 100, "dynamic", 100), (68, 36, "dynamic", 300)])
+def test_fsr_parity(H, W, kind, K):
+    R = need_gpu()
+    f, m, meas = frame(3, H, W, kind)
+    vals = meas.astype(np.float64)
+    ora, gaps = O.fsr_frame(vals, m, K=K)
+    out, out_u8 = run_gpu(R, vals, m, K=K)
+    worst, namb, nb = compare_fsr(out, ora, gaps)
+    print(f"FSR {H}x{W} {kind} K={K}: max|gpu-oracle| {worst:.2e} over unambiguous blocks, "
+          f"{namb}/{nb} tie-ambiguous")
+    assert worst <= FSR_TOL
+    assert namb <= 0.05 * nb
+    sl = (slice(8, -8), slice(8, -8))
+    assert abs(O.psnr(f[sl], out[sl], 0) - O.psnr(f[sl], ora[sl], 0)) <= PSNR_TOL
+    assert (out_u8 == O.quantize(out)).all()
+    assert (out[m == 1] == meas[m == 1]).all()
+
+
+def test_fsr_projected_classes_both_overwrites():
+    R = need_gpu()
+    f, m, meas = frame(4, 96, 64)
+    rng = np.random.default_rng(0)
+    cls = m.copy()
+    proj = (m == 0) & (rng.random(m.shape) < 0.4)
+    cls[proj] = 2
+    vals = meas.astype(np.float64)
+    vals[proj] = f[proj] + rng.uniform(-0.5, 0.5, proj.sum())    # non-integer projected means
+    vals = vals.astype(np.float32).astype(np.float64)              # what the float32 plane holds
+    for ow in ("dfsr", "rfsr"):
+        for pw in (1.0, 0.5):
+            ora, gaps = O.fsr_frame(vals, cls, K=60, overwrite=ow, proj_weight=pw)
+            out, _ = run_gpu(R, vals, cls, K=60, overwrite=ow, pw=pw)
+            worst, namb, nb = compare_fsr(out, ora, gaps)
+            assert worst <= FSR_TOL, (ow, pw, worst)
+            if ow == "rfsr":
+                assert (out[proj] == vals[proj].astype(np.float32)).all()
+
+
+@pytest.mark.parametrize("K", [1, 20])
+def test_fsr_constant_closed_form(K):
+    """Constant scene: DC is chosen every iteration, model c (1 - (1-gamma)^K)."""
+    R = need_gpu()
+    rng = np.random.default_rng(1)
+    m = synth.fixed_mask(64, 64, rng)
+    vals = np.where(m == 1, 100.0, 0.0)
+    out, _ = run_gpu(R, vals, m, K=K)
+    expect = 100.0 * (1 - 0.5 ** K)
+    assert np.max(np.abs(out[m == 0] - expect)) < 1e-3
+    assert (out[m == 1] == 100.0).all()
+
+
+def test_fsr_garbage_invariance_and_determinism():
+    R = need_gpu()
+    f, m, meas = frame(5, 64, 96)
+    vals = meas.astype(np.float32)
+    out1, _ = run_gpu(R, vals, m)
+    g = vals.copy()
+    g[m == 0] = np.nan
+    out2, _ = run_gpu(R, g, m)
+    out3, _ = run_gpu(R, vals, m)
+    assert np.array_equal(out1, out2) and np.array_equal(out1, out3)
+
+
+def test_fsr_edge_cases():
+    R = need_gpu()
+    # single block frame
+    m = np.array([[1, 0, 1, 0], [0, 0, 0, 0], [0, 1, 0, 1], [0, 0, 0, 0]], np.uint8)
+    vals = np.where(m == 1, 50.0, 0.0)
+    ora, _ = O.fsr_frame(vals, m, K=10)
+    out, _ = run_gpu(R, vals, m, K=10)
+    assert np.max(np.abs(out - ora)) < FSR_TOL
+    # K = 0: model 0 except the overwrite
+    f, m2, meas = frame(6, 32, 32)
+    out0, _ = run_gpu(R, meas.astype(np.float32), m2, K=0)
+    assert (out0[m2 == 0] == 0).all() and (out0[m2 == 1] == meas[m2 == 1]).all()
+    # no samples at all
+    z, _ = run_gpu(R, np.zeros((8, 8), np.float32), np.zeros((8, 8), np.uint8), K=5)
+    assert (z == 0).all()
+
+
+def test_fsr_full_hd_sampled_blocks():
+    """1920x1080 frame in the benchmark's launch configuration; the oracle
+    recomputes a seeded sample of blocks one by one."""
+    R = need_gpu()
+    H, W = 1080, 1920
+    f, m = synth.workload_c2(n=1, h=H, w=W)
+    meas = synth.measured(f, m)[0]
+    vals = meas.astype(np.float64)
+    out, _ = run_gpu(R, vals, m[0], K=100)
+    rng = np.random.default_rng(7)
+    blocks = np.stack([rng.integers(0, H // 4, 256), rng.integers(0, W // 4, 256)], axis=1)
+    blocks[:4] = [[0, 0], [H // 4 - 1, W // 4 - 1], [0, W // 4 - 1], [H // 4 - 1, 0]]
+    ora_b, gaps = O.fsr.fsr_blocks_out(vals, m[0], blocks, K=100)
+    got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
+    d = np.abs(got - ora_b).max(axis=(1, 2))
+    amb = gaps < 1e-5
+    print(f"1080p sample: max {d[~amb].max():.2e}, ambiguous {amb.sum()}/256")
+    assert d[~amb].max() <= FSR_TOL
+    assert amb.sum() <= 0.05 * 256
