@@ -145,6 +145,8 @@ rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, 
         if (stage_events && e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s);
     };
     record(0);
+    FsrTables* tab = reinterpret_cast<FsrTables*>(base + L.tables);
+    if (e == hipSuccess) e = launch_fsr_tables(tab, fsr->rho, s);
     ProjRef refs[3];
     for (int k = 0; k < nref && e == hipSuccess; ++k) {
         int8_t* a = reinterpret_cast<int8_t*>(base + L.ref[k][0]);
@@ -159,8 +161,6 @@ rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, 
     uint8_t* cls = base + L.cls;
     if (e == hipSuccess) e = launch_project(cur, cur_mask, H, W, pitch, nref, refs, W, values, cls, s);
     record(2);
-    FsrTables* tab = reinterpret_cast<FsrTables*>(base + L.tables);
-    if (e == hipSuccess) e = launch_fsr_tables(tab, fsr->rho, s);
     // FSR reads values/cls (workspace, pitch W) and writes with the caller's pitch.
     if (e == hipSuccess) e = launch_fsr(values, cls, H, W, W, *fsr, tab, out, out_u8, pitch, s);
     record(3);

@@ -140,11 +140,11 @@ def video_regions(n: int, h: int, w: int, rng: np.random.Generator, grid: int = 
     margin = vmax * max(n - 1, 0) + 1
     ch, cw = h + 2 * margin, w + 2 * margin
 
-    def texture():
-        return (128.0 + 40.0 * bandlimited_noise(ch, cw, 4.0, rng)
-                + 30.0 * bandlimited_noise(ch, cw, 32.0, rng))
+    def texture(th, tw):
+        return (128.0 + 40.0 * bandlimited_noise(th, tw, 4.0, rng)
+                + 30.0 * bandlimited_noise(th, tw, 32.0, rng))
 
-    tex = texture()
+    tex = texture(ch, cw)
     ry = (np.arange(h) * grid) // h
     rx = (np.arange(w) * grid) // w
     vel = rng.integers(-vmax, vmax + 1, size=(grid, grid, 2))
@@ -157,7 +157,7 @@ def video_regions(n: int, h: int, w: int, rng: np.random.Generator, grid: int = 
         y0 = int(rng.integers(0, max(h - side, 1)))
         x0 = int(rng.integers(0, max(w - side, 1)))
         sv = rng.integers(-vmax, vmax + 1, size=2)
-        squares.append((side, y0, x0, sv, texture()))
+        squares.append((side, y0, x0, sv, texture(side, side)))   # moves with the square
         area += side * side
     yy = np.arange(h)[:, None]
     xx = np.arange(w)[None, :]
@@ -170,8 +170,7 @@ def video_regions(n: int, h: int, w: int, rng: np.random.Generator, grid: int = 
             xs = np.arange(max(tx, 0), min(tx + side, w))
             if ys.size == 0 or xs.size == 0:
                 continue
-            f[ys[:, None], xs[None, :]] = stex[ys[:, None] - t * sv[0] + margin,
-                                               xs[None, :] - t * sv[1] + margin]
+            f[ys[:, None], xs[None, :]] = stex[ys[:, None] - ty, xs[None, :] - tx]
         frames[t] = _to_u8(f)
     return frames
 
