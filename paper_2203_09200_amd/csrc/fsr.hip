@@ -15,7 +15,7 @@
 //                real); R stays in registers (16 bins per lane), W goes to a
 //                32x32 LDS table
 //   4. K greedy iterations: wave argmax of |R_k|^2 (first in row-major order on
-//                ties) with DPP row reductions, dlt = gamma R_b / W0,
+//                ties) with DPP and permlane reductions, dlt = gamma R_b / W0,
 //                R_k -= dlt * W(k - b); the (b, dlt) list goes to LDS
 //   5. synthesis Re sum dlt phi_b on the 16 block pixels, overwrite, store.
 //
@@ -86,29 +86,45 @@ __device__ __forceinline__ void fft16(T (&re)[16], T (&im)[16], const T* __restr
 
 // 32-point forward DFT of x[m], m = i + 16 h held by the lane pair (h=0, h=1)
 // at register i.  Afterwards register k' of lane h holds X[2 k' + h].
-template <typename T>
-__device__ __forceinline__ void fft32_pair(T (&re)[16], T (&im)[16], int h, const T* __restrict__ tw) {
+__device__ __forceinline__ void fft32_pair(double (&re)[16], double (&im)[16], int h,
+                                           const double* __restrict__ tw) {
+    const double sgn = h ? -1.0 : 1.0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const T pr = __shfl_xor(re[i], 32);
-        const T pi = __shfl_xor(im[i], 32);
+        const double pr = __shfl_xor(re[i], 32);
+        const double pi = __shfl_xor(im[i], 32);
         // h = 0: x[i] + x[i+16];  h = 1: (x[i] - x[i+16]) * w32^i
-        const T ur = h ? pr - re[i] : re[i] + pr;
-        const T ui = h ? pi - im[i] : im[i] + pi;
-        const T cr = h ? tw[2 * i] : T(1);
-        const T ci = h ? tw[2 * i + 1] : T(0);
-        re[i] = ur * cr - ui * ci;
-        im[i] = ur * ci + ui * cr;
+        const double ur = fma(sgn, re[i], pr);
+        const double ui = fma(sgn, im[i], pi);
+        if (i == 0) {
+            re[i] = ur;
+            im[i] = ui;
+        } else {
+            const double twr = tw[2 * i], twi = tw[2 * i + 1];   // uniform loads, then select
+            const double cr = h ? twr : 1.0;
+            const double ci = h ? twi : 0.0;
+            re[i] = ur * cr - ui * ci;
+            im[i] = ur * ci + ui * cr;
+        }
     }
     fft16(re, im, tw);
 }
 
+// v_max_f64 on values that are never NaN.  Written as a single instruction:
+// the compiler otherwise canonicalises the bit-assembled operands first.
+__device__ __forceinline__ double max_f64(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Row permutation of a double with DPP; every lane reads a valid source lane
+// for the patterns used here, so no 'old' value needs initialising.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
-    const uint64_t u = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = dpp_u32<CTRL>((uint32_t)u, 0u);
-    const uint32_t hi = dpp_u32<CTRL>((uint32_t)(u >> 32), 0u);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double((int)hi, (int)lo);
 }
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
@@ -117,13 +133,44 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Maximum of non-negative doubles over the 64 lanes (wave-uniform result).
-__device__ __forceinline__ double wave_max_f64(double v) {
-    v = fmax(v, dpp_f64<kDppQuadXor1>(v));
-    v = fmax(v, dpp_f64<kDppQuadXor2>(v));
-    v = fmax(v, dpp_f64<kDppRowHalfMirror>(v));
-    v = fmax(v, dpp_f64<kDppRowMirror>(v));
-    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+// Maximum of non-negative doubles over the 64 lanes, left in every lane:
+// butterfly inside each 16-lane row with DPP, then across rows with the gfx950
+// permlane swaps (odd rows <-> even rows, upper half <-> lower half).
+__device__ __forceinline__ double pair_max(double v, int which) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    uint32_t a_lo, a_hi, b_lo, b_hi;
+    if (which == 16) {
+        const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        a_lo = pl[0]; b_lo = pl[1]; a_hi = ph[0]; b_hi = ph[1];
+    } else {
+        const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        a_lo = pl[0]; b_lo = pl[1]; a_hi = ph[0]; b_hi = ph[1];
+    }
+    const double a = __longlong_as_double((long long)(((uint64_t)a_hi << 32) | a_lo));
+    const double b = __longlong_as_double((long long)(((uint64_t)b_hi << 32) | b_lo));
+    return max_f64(a, b);
+}
+
+__device__ __forceinline__ double wave_allmax_f64(double v) {
+    v = max_f64(v, dpp_f64<kDppQuadXor1>(v));
+    v = max_f64(v, dpp_f64<kDppQuadXor2>(v));
+    v = max_f64(v, dpp_f64<kDppRowHalfMirror>(v));
+    v = max_f64(v, dpp_f64<kDppRowMirror>(v));
+    v = pair_max(v, 16);
+    return pair_max(v, 32);
+}
+
+// Energy with the bin's support row k1 packed into the 5 low mantissa bits
+// as 31 - k1: the maximum over packed energies is the maximum energy with
+// ties (at 2^-47 relative resolution, far below float64 rounding of the
+// residual) going to the smallest k1, and k1 is read back from the maximum.
+__device__ __forceinline__ double pack_energy(double e, uint32_t code) {
+    const int hi = __double2hiint(e);
+    const int lo = (int)(((uint32_t)__double2loint(e) & ~31u) | code);
+    return __hiloint2double(hi, lo);
 }
 
 constexpr int kPlane = 33;                       // padded row length of a transpose plane
@@ -144,7 +191,9 @@ __global__ void fsr_tables_kernel(FsrTables* t, double rho) {
     }
 }
 
-__global__ __launch_bounds__(64) void fsr_block_kernel(
+// LDS (the 16 KB W table per block) caps residency at two waves per SIMD;
+// telling the compiler so lets it keep the LDS reads of an iteration in flight.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void fsr_block_kernel(
     const float* __restrict__ values, const uint8_t* __restrict__ cls, int H, int W,
     int64_t pitch, const FsrTables* __restrict__ tab, float* __restrict__ out,
     uint8_t* __restrict__ out_u8, int64_t out_pitch, int K, double gamma, double projw,
@@ -171,21 +220,26 @@ __global__ __launch_bounds__(64) void fsr_block_kernel(
     }
 
     // 1. gather: lane (h, c) holds support rows m = i + 16 h of column c.
+    //    Loads use clamped coordinates (always in bounds); positions outside
+    //    the frame get weight 0.
     double zr[16], zi[16];
     {
         const int y0 = 4 * bi - 14, x = 4 * bj - 14 + c;
         const bool xin = (unsigned)x < (unsigned)W;
+        const int xc = min(max(x, 0), W - 1);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int m = i + 16 * h;
             const int y = y0 + m;
             const bool in = xin && (unsigned)y < (unsigned)H;
-            const int64_t off = in ? (int64_t)y * pitch + x : 0;
-            const uint32_t k = in ? (uint32_t)cls[off] : 0u;
-            const bool known = k == 1u || k == 2u;
+            const int64_t off = (int64_t)min(max(y, 0), H - 1) * pitch + xc;
+            const uint32_t k = cls[off];
+            const float v = values[off];
+            const bool known = in && (k == 1u || k == 2u);
+            const double rw = tab->rho[m * 32 + c];
             const double a = (k == 1u) ? 1.0 : projw;
-            const double wv = known ? a * tab->rho[m * 32 + c] : 0.0;
-            const double sv = known ? (double)values[off] : 0.0;
+            const double wv = known ? a * rw : 0.0;
+            const double sv = known ? (double)v : 0.0;
             zr[i] = wv * sv;
             zi[i] = wv;
         }
@@ -246,39 +300,46 @@ __global__ __launch_bounds__(64) void fsr_block_kernel(
 
     // 4. greedy iterations.
     const double g = (W0 > 0.0) ? gamma / W0 : 0.0;
-    double lbe = -1.0;
-    int lbj = 0;
+    double lbe = -1.0;   // packed local maximum
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const double e = fma(Rr[j], Rr[j], Ri[j] * Ri[j]);
-        if (e > lbe) { lbe = e; lbj = j; }
-    }
+    for (int j = 0; j < 16; ++j)
+        lbe = max_f64(lbe, pack_energy(fma(Rr[j], Rr[j], Ri[j] * Ri[j]), (uint32_t)(31 - 16 * h - j)));
     const uint8_t* Tb = smem;
     for (int it = 0; it < K; ++it) {
-        const double M = wave_max_f64(lbe);
-        const uint32_t cand = (lbe == M) ? (uint32_t)((lbj + 16 * h) * 32 + c) : 0xFFFFFFFFu;
-        const uint32_t bflat = wave_min_u32(cand);
-        const int b1 = (int)(bflat >> 5), b2 = (int)(bflat & 31);
-        const int owner = b2 + ((b1 >> 4) << 5);
+        const double M = wave_allmax_f64(lbe);
+        const uint32_t mlo = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)(uint32_t)(uint64_t)__double_as_longlong(M));
+        const int b1 = 31 - (int)(mlo & 31u);
+        // lanes holding the maximum all own row b1; the first is the smallest column
+        const unsigned long long hit = __ballot(lbe == M);
+        const int owner = hit ? (int)__builtin_ctzll(hit) : (b1 >> 4) << 5;
+        const int b2 = owner & 31;
         const int jb = b1 & 15;
         const double vr = Rr[jb], vi = Ri[jb];   // jb is wave-uniform: indexed register move
         const double dr = g * readlane_f64(vr, owner);
         const double di = g * readlane_f64(vi, owner);
-        if (lane == 0) list[it] = make_float4(__uint_as_float(bflat), (float)dr, (float)di, 0.0f);
+        if (lane == 0)
+            list[it] = make_float4(__uint_as_float((uint32_t)(b1 * 32 + b2)), (float)dr, (float)di, 0.0f);
         const uint32_t L = ((uint32_t)h << 13) | ((uint32_t)((c - b2) & 31) << 4);
         lbe = -1.0;
+        // issue all 16 table reads before the arithmetic so that their LDS
+        // latency overlaps
+        double2 wt[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const uint32_t S = (uint32_t)((j - b1) & 31) << 9;   // wave-uniform row part
-            const double2 wv = *reinterpret_cast<const double2*>(Tb + (S ^ L));
+            wt[j] = *reinterpret_cast<const double2*>(Tb + (S ^ L));
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const double2 wv = wt[j];
             double xr = fma(-dr, wv.x, Rr[j]);
             xr = fma(di, wv.y, xr);
             double xi = fma(-dr, wv.y, Ri[j]);
             xi = fma(-di, wv.x, xi);
             Rr[j] = xr;
             Ri[j] = xi;
-            const double e = fma(xr, xr, xi * xi);
-            if (e > lbe) { lbe = e; lbj = j; }
+            lbe = max_f64(lbe, pack_energy(fma(xr, xr, xi * xi), (uint32_t)(31 - 16 * h - j)));
         }
     }
     __syncthreads();

@@ -1,0 +1,117 @@
+"""Small drivers to run under rocprofv3 (counter and trace collection).
+
+    python -m paper_2203_09200_amd.profiling fsr  [--reps 3]   # FSR kernel, 1080p workload frame
+    python -m paper_2203_09200_amd.profiling copy [--mib 1024] # plain device copy of known size
+
+`fsr` launches fsr_blocks on one frame of the 1920x1080 benchmark workload
+(dynamic mask, K = 100) `reps` times.  `copy` copies a buffer of the given
+size once with torch (reads and writes exactly `mib` MiB), so FETCH_SIZE and
+WRITE_SIZE of the same run calibrate the counters' units.
+
+`record` writes profiles/fsr_block_kernel_1080p_traffic.json from the
+per-dispatch counter values read off the rocprofv3 CSVs, keyed by the
+SHA-256 of the kernel source, so that bench.py reports `traffic` only while
+the kernel is unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def run_fsr(reps: int):
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    import synth
+    import paper_2203_09200_amd as R
+    f, m = synth.workload_c2(n=1)
+    meas = synth.measured(f, m)[0]
+    v = torch.from_numpy(meas.astype(np.float32)).cuda()
+    c = torch.from_numpy(m[0]).cuda()
+    for _ in range(reps):
+        R.fsr_blocks(v, c, R.FSRParams(iters=100))
+    torch.cuda.synchronize()
+    print(f"fsr_blocks x{reps} done", flush=True)
+
+
+def run_copy(mib: int):
+    import torch
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty(n, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {mib} MiB", flush=True)
+
+
+def _counter_per_dispatch(csv_path: str, kernel_substr: str, counter: str):
+    vals = []
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            name = row.get("Kernel_Name") or row.get("Kernel-Name") or ""
+            if kernel_substr in name and row.get("Counter_Name") == counter:
+                vals.append(float(row["Counter_Value"]))
+    return vals
+
+
+def record(fsr_fetch_csv, fsr_write_csv, copy_fetch_csv, copy_write_csv, copy_mib, copy_kernel):
+    ff = _counter_per_dispatch(fsr_fetch_csv, "fsr_block_kernel", "FETCH_SIZE")
+    fw = _counter_per_dispatch(fsr_write_csv, "fsr_block_kernel", "WRITE_SIZE")
+    cf = _counter_per_dispatch(copy_fetch_csv, copy_kernel, "FETCH_SIZE")
+    cw = _counter_per_dispatch(copy_write_csv, copy_kernel, "WRITE_SIZE")
+    nbytes = copy_mib << 20
+    # counters read in KiB; the copy of known size fixes the scale of each
+    s_fetch = nbytes / max(cf) if cf else None
+    s_write = nbytes / max(cw) if cw else None
+    fetch_b = sum(ff) / len(ff) * s_fetch
+    write_b = sum(fw) / len(fw) * s_write
+    with open(os.path.join(HERE, "csrc", "fsr.hip"), "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    rec = {"kernel": "fsr_block_kernel", "workload": "1920x1080 frame, dynamic mask, K=100",
+           "kernel_sha256": digest, "fetch_kib_per_dispatch": sum(ff) / len(ff),
+           "write_kib_per_dispatch": sum(fw) / len(fw), "copy_mib": copy_mib,
+           "copy_fetch_kib": max(cf), "copy_write_kib": max(cw),
+           "fetch_scale_bytes_per_unit": s_fetch, "write_scale_bytes_per_unit": s_write,
+           "bytes_per_launch": fetch_b + write_b}
+    out = os.path.join(ROOT, "profiles", "fsr_block_kernel_1080p_traffic.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a1 = sub.add_parser("fsr")
+    a1.add_argument("--reps", type=int, default=3)
+    a2 = sub.add_parser("copy")
+    a2.add_argument("--mib", type=int, default=1024)
+    a3 = sub.add_parser("record")
+    a3.add_argument("fsr_fetch_csv")
+    a3.add_argument("fsr_write_csv")
+    a3.add_argument("copy_fetch_csv")
+    a3.add_argument("copy_write_csv")
+    a3.add_argument("--copy-mib", type=int, default=1024)
+    a3.add_argument("--copy-kernel", default="copyBuffer")
+    a = ap.parse_args(argv)
+    if a.cmd == "fsr":
+        run_fsr(a.reps)
+    elif a.cmd == "copy":
+        run_copy(a.mib)
+    else:
+        record(a.fsr_fetch_csv, a.fsr_write_csv, a.copy_fetch_csv, a.copy_write_csv, a.copy_mib,
+               a.copy_kernel)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
