@@ -363,11 +363,41 @@ __global__ void rme_accept_kernel(AcceptIO io, int H, int W, const int8_t* __res
     }
 }
 
-// RMC (DENSE, offsets [-rr, rr]^2) and FRMC ({-7,-3,-1,0,1,3,7}^2): accept
-// iff S(p,v)/n(p) < S(p+d, v-d)/n(p+d) for every red d with p+d in the frame.
-// Reds are tried in raster order and the test stops at the first loser.
-// CASCADE: only pixels already accepted (by NNC) are tested, the rest stay 0.
-template <bool DENSE, bool CASCADE>
+// RMC (DENSE, offsets [-rr, rr]^2) and FRMC ({-7,-3,-1,0,1,3,7}^2) at pixel p
+// with vector (a, b): accept iff S(p,v)/n(p) < S(p+d, v-d)/n(p+d) for every
+// red d with p+d in the frame.  Reds are tried in raster order and the test
+// stops at the first loser.  evals counts the red costs evaluated.
+template <bool DENSE>
+__device__ __forceinline__ bool reverse_test(const RevCtx& c, const uint8_t* __restrict__ ref,
+                                             int64_t pitch, int py, int px, int a, int b,
+                                             uint32_t Sg, uint32_t ng, int rr,
+                                             unsigned long long& evals) {
+    uint32_t r[4];
+    ref_template(ref, c.H, c.W, pitch, py + a, px + b, r);
+    bool ok = true;
+    // FRMC offsets {-7,-3,-1,0,1,3,7}: sign(i-3) * (2^|i-3| - 1)
+    const int n1 = DENSE ? 2 * rr + 1 : 7;
+    for (int iy = 0; iy < n1 && ok; ++iy) {
+        const int dy = DENSE ? iy - rr : (iy < 3 ? -1 : 1) * ((1 << abs(iy - 3)) - 1);
+        const int sy = py + dy;
+        if ((unsigned)sy >= (unsigned)c.H) continue;
+        for (int ix = 0; ix < n1; ++ix) {
+            const int dx = DENSE ? ix - rr : (ix < 3 ? -1 : 1) * ((1 << abs(ix - 3)) - 1);
+            const int sx = px + dx;
+            if ((dy | dx) == 0 || (unsigned)sx >= (unsigned)c.W) continue;
+            const uint32_t S = rev_cost(c, r, sy, sx);
+            const uint32_t n = c.nmap[(int64_t)sy * c.W + sx];
+            ++evals;
+            if (S * ng <= Sg * n) { ok = false; break; }
+        }
+    }
+    return ok;
+}
+
+// RMC / FRMC over every pixel (stand-alone checks).  With io.ref_mask set,
+// only projectable pixels (missing now, measured at p+v) are tested; the
+// decision elsewhere is 0.
+template <bool DENSE>
 __global__ __launch_bounds__(256) void rmc_kernel(
     RevCtx c, AcceptIO io, const uint8_t* __restrict__ ref, const uint16_t* __restrict__ cost,
     int64_t cost_pitch, int rr, unsigned long long* __restrict__ counters) {
@@ -375,37 +405,17 @@ __global__ __launch_bounds__(256) void rmc_kernel(
     unsigned long long evals = 0, checked = 0, accepted = 0;
     if (e < c.H * c.W) {
         const int py = e / c.W, px = e - py * c.W;
-        bool ok = true;
-        if (CASCADE) ok = io.accept[(int64_t)py * io.acc_pitch + px] != 0;
         const int a = io.mv_a[(int64_t)py * io.mv_pitch + px];
         const int b = io.mv_b[(int64_t)py * io.mv_pitch + px];
-        if (ok && io.ref_mask) {
-            // Only projectable pixels matter: missing now, measured at p+v.
+        bool ok = true;
+        if (io.ref_mask) {
             ok = io.cur_mask[(int64_t)py * io.pitch + px] == 0 &&
                  io.ref_mask[(int64_t)(py + a) * io.pitch + (px + b)] != 0;
         }
         if (ok) {
             checked = 1;
-            uint32_t r[4];
-            ref_template(ref, c.H, c.W, io.pitch, py + a, px + b, r);
-            const uint32_t Sg = cost[(int64_t)py * cost_pitch + px];
-            const uint32_t ng = c.nmap[(int64_t)py * c.W + px];
-            // FRMC offsets {-7,-3,-1,0,1,3,7}: sign(i-3) * (2^|i-3| - 1)
-            const int n1 = DENSE ? 2 * rr + 1 : 7;
-            for (int iy = 0; iy < n1 && ok; ++iy) {
-                const int dy = DENSE ? iy - rr : (iy < 3 ? -1 : 1) * ((1 << abs(iy - 3)) - 1);
-                const int sy = py + dy;
-                if ((unsigned)sy >= (unsigned)c.H) continue;
-                for (int ix = 0; ix < n1; ++ix) {
-                    const int dx = DENSE ? ix - rr : (ix < 3 ? -1 : 1) * ((1 << abs(ix - 3)) - 1);
-                    const int sx = px + dx;
-                    if ((dy | dx) == 0 || (unsigned)sx >= (unsigned)c.W) continue;
-                    const uint32_t S = rev_cost(c, r, sy, sx);
-                    const uint32_t n = c.nmap[(int64_t)sy * c.W + sx];
-                    ++evals;
-                    if (S * ng <= Sg * n) { ok = false; break; }
-                }
-            }
+            ok = reverse_test<DENSE>(c, ref, io.pitch, py, px, a, b, cost[(int64_t)py * cost_pitch + px],
+                                     c.nmap[(int64_t)py * c.W + px], rr, evals);
         }
         io.accept[(int64_t)py * io.acc_pitch + px] = ok;
         accepted = ok;
@@ -418,6 +428,73 @@ __global__ __launch_bounds__(256) void rmc_kernel(
             atomicAdd(counters + RFSR_CNT_CHECK_COSTS, evals);
             atomicAdd(counters + RFSR_CNT_CHECKED_PIXELS, checked);
             atomicAdd(counters + RFSR_CNT_ACCEPTED, accepted);
+        }
+    }
+}
+
+// FRMC after NNC (the cascade).  A workgroup owns a run of kFrmcTile raster
+// pixels: it collects the pixels that need the test (NNC accepted and, in
+// the frame path, projectable) into an LDS list, then runs FRMC over that
+// list with all its threads, so that waves stay full although most pixels
+// need no test.  Every pixel of the run gets its decision written.
+constexpr int kFrmcTile = 2048;
+
+__global__ __launch_bounds__(256) void frmc_tile_kernel(
+    RevCtx c, AcceptIO io, const uint8_t* __restrict__ ref, const uint16_t* __restrict__ cost,
+    int64_t cost_pitch, unsigned long long* __restrict__ counters) {
+    __shared__ int s_list[kFrmcTile];
+    __shared__ unsigned s_n;
+    const int tid = threadIdx.x;
+    const int npx = c.H * c.W;
+    const int e0 = blockIdx.x * kFrmcTile;
+    if (tid == 0) s_n = 0u;
+    __syncthreads();
+    unsigned long long checked = 0;
+    for (int k = 0; k < kFrmcTile / 256; ++k) {
+        const int e = e0 + k * 256 + tid;
+        bool need = false;
+        if (e < npx) {
+            const int y = e / c.W, x = e - y * c.W;
+            need = io.accept[(int64_t)y * io.acc_pitch + x] != 0;   // NNC decision
+            if (need && io.ref_mask) {
+                const int va = io.mv_a[(int64_t)y * io.mv_pitch + x];
+                const int vb = io.mv_b[(int64_t)y * io.mv_pitch + x];
+                need = io.cur_mask[(int64_t)y * io.pitch + x] == 0 &&
+                       io.ref_mask[(int64_t)(y + va) * io.pitch + (x + vb)] != 0;
+            }
+            if (!need) io.accept[(int64_t)y * io.acc_pitch + x] = 0;
+        }
+        // wave-aggregated append to the LDS list
+        const unsigned long long m = __ballot(need);
+        const int lane = tid & 63;
+        unsigned base = 0;
+        if (lane == 0 && m) base = atomicAdd(&s_n, (unsigned)__popcll(m));
+        base = __shfl(base, 0);
+        if (need) s_list[base + __popcll(m & ((1ull << lane) - 1ull))] = e;
+        checked += need;
+    }
+    __syncthreads();
+    const unsigned n = s_n;
+    unsigned long long evals = 0, accepted = 0;
+    for (unsigned i = tid; i < n; i += 256) {
+        const int e = s_list[i];
+        const int py = e / c.W, px = e - py * c.W;
+        const int a = io.mv_a[(int64_t)py * io.mv_pitch + px];
+        const int b = io.mv_b[(int64_t)py * io.mv_pitch + px];
+        const bool ok = reverse_test<false>(c, ref, io.pitch, py, px, a, b,
+                                            cost[(int64_t)py * cost_pitch + px],
+                                            c.nmap[(int64_t)py * c.W + px], 0, evals);
+        io.accept[(int64_t)py * io.acc_pitch + px] = ok;
+        accepted += ok;
+    }
+    if (counters) {
+        evals = wave_sum_u64(evals);
+        accepted = wave_sum_u64(accepted);
+        checked = wave_sum_u64(checked);
+        if ((tid & 63) == 0) {
+            atomicAdd(counters + RFSR_CNT_CHECK_COSTS, evals);
+            atomicAdd(counters + RFSR_CNT_ACCEPTED, accepted);
+            atomicAdd(counters + RFSR_CNT_CHECKED_PIXELS, checked);
         }
     }
 }
@@ -465,6 +542,7 @@ __global__ void median_kernel(const int8_t* __restrict__ a, const int8_t* __rest
     mb[e] = (int8_t)median9(vb);
 }
 
+// NNC decision (the cascade's FRMC reads it back from `accept`).
 __global__ void nnc_kernel(const int8_t* __restrict__ ma, const int8_t* __restrict__ mb, int H,
                            int W, uint8_t* __restrict__ accept, int64_t acc_pitch,
                            unsigned long long* counters, bool count) {
@@ -625,26 +703,27 @@ hipError_t run_motion_check(const uint8_t* cur, const uint8_t* cur_mask, const u
             break;
         }
         case RFSR_CHECK_RMC:
-            hipLaunchKernelGGL((rmc_kernel<true, false>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref,
-                               cost, cost_pitch, rr, counters);
+            hipLaunchKernelGGL((rmc_kernel<true>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref, cost,
+                               cost_pitch, rr, counters);
             break;
         case RFSR_CHECK_FRMC:
-            hipLaunchKernelGGL((rmc_kernel<false, false>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref,
-                               cost, cost_pitch, rr, counters);
+            hipLaunchKernelGGL((rmc_kernel<false>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref, cost,
+                               cost_pitch, rr, counters);
             break;
         case RFSR_CHECK_NNC:
         case RFSR_CHECK_NNC_FRMC: {
+            const bool cascade = check == RFSR_CHECK_NNC_FRMC;
             int8_t* ma = reinterpret_cast<int8_t*>(base + L.ma);
             int8_t* mb = reinterpret_cast<int8_t*>(base + L.mb);
             hipLaunchKernelGGL(median_kernel, dim3(grid1(npx)), dim3(256), 0, s, mv_a, mv_b, mv_pitch, H, W,
                                ma, mb);
             if ((err = hipGetLastError()) != hipSuccess) return err;
             hipLaunchKernelGGL(nnc_kernel, dim3(grid1(npx)), dim3(256), 0, s, ma, mb, H, W, accept, acc_pitch,
-                               counters, check == RFSR_CHECK_NNC);
-            if (check == RFSR_CHECK_NNC_FRMC) {
+                               counters, !cascade);
+            if (cascade) {
                 if ((err = hipGetLastError()) != hipSuccess) return err;
-                hipLaunchKernelGGL((rmc_kernel<false, true>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref,
-                                   cost, cost_pitch, rr, counters);
+                hipLaunchKernelGGL(frmc_tile_kernel, dim3(grid1(npx, kFrmcTile)), dim3(256), 0, s, rc, io, ref,
+                                   cost, cost_pitch, counters);
             }
             break;
         }
