@@ -173,6 +173,68 @@ rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, 
                                    float* out, uint8_t* out_u8, void* const* stage_events,
                                    void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------- batches ---
+ * Many independent streams of recursive reconstruction advance one time step
+ * together: every frame of the batch is a separate rfsr_reconstruct_frame
+ * problem (its own size, mask, references and outputs; Fig. 1 per stream),
+ * but the whole batch runs as ONE launch chain (window planes, forward ME,
+ * checks, projection, FSR: each stage one kernel over all frames), so that
+ * small and large frames fill the GPU together and the chain can be captured
+ * once in a HIP graph and replayed.  Results equal those of
+ * rfsr_reconstruct_frame on each frame alone, bit for bit. */
+typedef struct {
+    const uint8_t* cur;           /* uint8 H x W measured frame (device)        */
+    const uint8_t* cur_mask;      /* uint8 H x W mask (device)                  */
+    const uint8_t* ref_recon[3];  /* nref reconstructions, index k = lag k+1    */
+    const uint8_t* ref_meas[3];   /* their measured frames                      */
+    const uint8_t* ref_mask[3];   /* their masks                                */
+    float* out;                   /* float32 H x W out                          */
+    uint8_t* out_u8;              /* uint8 H x W out (nullable)                 */
+    int32_t nref;                 /* 0..3                                       */
+    int32_t H, W;                 /* multiples of 4, at most 16384              */
+    int32_t reserved;             /* set to 0                                   */
+    int64_t pitch;                /* elements, shared by this frame's planes    */
+} rfsr_frame_desc;
+
+/* Workspace bytes of rfsr_reconstruct_batch for these frames (1..4096 of
+ * them); 0 if the descriptors are invalid. */
+size_t rfsr_batch_workspace_bytes(const rfsr_frame_desc* frames, int32_t n,
+                                  const rfsr_me_params* me, const rfsr_fsr_params* fsr);
+
+/* Bytes of the batch's job-table image (a multiple of 256); 0 if invalid. */
+size_t rfsr_batch_table_bytes(const rfsr_frame_desc* frames, int32_t n);
+
+/* Writes the job-table image of the batch into the HOST buffer `image`
+ * (>= rfsr_batch_table_bytes bytes): a header, then the per-frame and
+ * per-reference jobs the kernels read (device pointers into the frames and
+ * into `workspace`, each job's first workgroup in the merged grids).
+ * `workspace` is only used as an address.  The caller copies the image to a
+ * device buffer (256-byte aligned) that it passes as `job_tables`; the image
+ * stays valid for every later call with the same descriptors, the same
+ * me->check and the same workspace (e.g. replays of a captured graph).  The
+ * header holds a hash of exactly these; kernels given an image whose hash
+ * differs from the call's skip all work (outputs are left unwritten).
+ * Errors: RFSR_EINVAL (bad descriptors, image too small), RFSR_EWORKSPACE
+ * (null or misaligned workspace), as rfsr_reconstruct_frame otherwise. */
+rfsr_status rfsr_batch_write_tables(const rfsr_frame_desc* frames, int32_t n,
+                                    const rfsr_me_params* me, const void* workspace,
+                                    void* image, size_t image_bytes);
+
+/* One time step of n streams: rfsr_reconstruct_frame on every frame of
+ * `frames`, as one chain of kernel launches on `stream`.
+ *   job_tables  DEVICE copy of the image rfsr_batch_write_tables wrote for
+ *               these descriptors, me->check and workspace (256-byte aligned)
+ *   workspace   device, >= rfsr_batch_workspace_bytes, 256-byte aligned
+ * The call only enqueues kernels and event records (no copies, no memsets),
+ * so it may be captured in a graph.
+ * stage_events: NULL or 4 events, as rfsr_reconstruct_frame (for the batch).
+ * Errors: as rfsr_reconstruct_frame; RFSR_EINVAL for a null or misaligned
+ * job_tables. */
+rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n,
+                                   const rfsr_me_params* me, const rfsr_fsr_params* fsr,
+                                   const void* job_tables, void* const* stage_events,
+                                   void* workspace, size_t ws_bytes, void* stream);
+
 /* Timing events for stage_events and benchmarks (thin wrappers of HIP
  * events).  rfsr_event_elapsed_ms waits for `stop`. */
 rfsr_status rfsr_event_create(void** event);

@@ -5,10 +5,10 @@ reconstruction of quarter-sampled video with fast motion consistency checks
 The computation lives in librfsr.so (HIP kernels behind the C ABI of
 include/rfsr.h); this package is its Python binding.
 """
-from ._lib import (CHECKS, COUNTER_NAMES, Event, FSRParams, MEParams, RfsrError, Sequence,
-                   Workspace, fsr_blocks, lib, motion_check, reconstruct_frame, workspace_bytes,
-                   LIB_PATH)
+from ._lib import (CHECKS, COUNTER_NAMES, Batch, BatchFrame, Event, FrameDesc, FSRParams, MEParams,
+                   RfsrError, Sequence, StreamSet, Workspace, fsr_blocks, lib, motion_check,
+                   reconstruct_frame, workspace_bytes, LIB_PATH)
 
-__all__ = ["CHECKS", "COUNTER_NAMES", "Event", "FSRParams", "MEParams", "RfsrError", "Sequence",
-           "Workspace", "fsr_blocks", "lib", "motion_check", "reconstruct_frame",
-           "workspace_bytes", "LIB_PATH"]
+__all__ = ["CHECKS", "COUNTER_NAMES", "Batch", "BatchFrame", "Event", "FrameDesc", "FSRParams",
+           "MEParams", "RfsrError", "Sequence", "StreamSet", "Workspace", "fsr_blocks", "lib",
+           "motion_check", "reconstruct_frame", "workspace_bytes", "LIB_PATH"]

@@ -66,6 +66,15 @@ class FSRParams:
                           self.rho, self.gamma, self.proj_weight)
 
 
+class FrameDesc(ctypes.Structure):
+    """rfsr_frame_desc: one frame of a batch (device pointers)."""
+    _fields_ = [("cur", ctypes.c_void_p), ("cur_mask", ctypes.c_void_p),
+                ("ref_recon", ctypes.c_void_p * 3), ("ref_meas", ctypes.c_void_p * 3),
+                ("ref_mask", ctypes.c_void_p * 3), ("out", ctypes.c_void_p), ("out_u8", ctypes.c_void_p),
+                ("nref", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("pitch", ctypes.c_int64)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -95,6 +104,18 @@ def lib():
                                          ctypes.c_int64, ctypes.POINTER(_MEParams),
                                          ctypes.POINTER(_FSRParams), _P, _P, ctypes.POINTER(_P),
                                          _P, ctypes.c_size_t, _P]
+    L.rfsr_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.rfsr_batch_workspace_bytes.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32,
+                                             ctypes.POINTER(_MEParams), ctypes.POINTER(_FSRParams)]
+    L.rfsr_batch_table_bytes.restype = ctypes.c_size_t
+    L.rfsr_batch_table_bytes.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32]
+    L.rfsr_batch_write_tables.restype = _STATUS
+    L.rfsr_batch_write_tables.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32,
+                                          ctypes.POINTER(_MEParams), _P, _P, ctypes.c_size_t]
+    L.rfsr_reconstruct_batch.restype = _STATUS
+    L.rfsr_reconstruct_batch.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32,
+                                         ctypes.POINTER(_MEParams), ctypes.POINTER(_FSRParams), _P,
+                                         ctypes.POINTER(_P), _P, ctypes.c_size_t, _P]
     L.rfsr_event_create.restype = _STATUS
     L.rfsr_event_create.argtypes = [ctypes.POINTER(_P)]
     L.rfsr_event_destroy.restype = _STATUS
@@ -318,3 +339,188 @@ class Sequence:
         if len(self.ring) > self.nref:
             self.ring.pop(0)
         return out, out_u8
+
+
+# ----------------------------------------------------------------- batches --
+@dataclass
+class BatchFrame:
+    """One frame of a batch: measured frame and mask, up to three references
+    (recon, meas, mask) for lags 1..3, and the output planes.  All planes of a
+    frame are uint8 (out: float32) device tensors sharing one row pitch."""
+    cur: torch.Tensor
+    mask: torch.Tensor
+    refs: tuple = ()
+    out: torch.Tensor | None = None
+    out_u8: torch.Tensor | None = None
+
+
+def _frame_desc(f: BatchFrame, i: int) -> FrameDesc:
+    _plane(f.cur, torch.uint8, f"frames[{i}].cur")
+    H, W = f.cur.shape
+    pitch = f.cur.stride(0)
+    planes = [f.cur, _plane(f.mask, torch.uint8, f"frames[{i}].mask", (H, W))]
+    if len(f.refs) > 3:
+        raise RfsrError(f"frames[{i}]: at most 3 references")
+    d = FrameDesc()
+    d.cur, d.cur_mask = f.cur.data_ptr(), f.mask.data_ptr()
+    for k, (r, m, b) in enumerate(f.refs):
+        for t, nm in ((r, "recon"), (m, "meas"), (b, "mask")):
+            planes.append(_plane(t, torch.uint8, f"frames[{i}].ref{k}.{nm}", (H, W)))
+        d.ref_recon[k], d.ref_meas[k], d.ref_mask[k] = r.data_ptr(), m.data_ptr(), b.data_ptr()
+    if f.out is None:
+        f.out = torch.empty_strided((H, W), (pitch, 1), dtype=torch.float32, device=f.cur.device)
+    planes.append(_plane(f.out, torch.float32, f"frames[{i}].out", (H, W)))
+    d.out = f.out.data_ptr()
+    if f.out_u8 is not None:
+        planes.append(_plane(f.out_u8, torch.uint8, f"frames[{i}].out_u8", (H, W)))
+        d.out_u8 = f.out_u8.data_ptr()
+    if any(p.stride(0) != pitch for p in planes):
+        raise RfsrError(f"frames[{i}]: all planes must share the row pitch")
+    if any(p.device != f.cur.device for p in planes):
+        raise RfsrError(f"frames[{i}]: planes on different devices")
+    d.nref, d.H, d.W, d.pitch = len(f.refs), H, W, pitch
+    return d
+
+
+class Batch:
+    """A fixed set of frames reconstructed together by rfsr_reconstruct_batch
+    (one launch chain for all frames).  The job tables are written once at
+    construction; `run()` enqueues the chain, `capture()` records it in a
+    CUDA/HIP graph whose replays recompute the same frames from whatever the
+    input planes hold at replay time.
+
+    workspace: optional uint8 device tensor (256-byte aligned, at least
+    `Batch.workspace_bytes(frames)`), which batches that never run at the
+    same time may share.
+    """
+
+    def __init__(self, frames, me: MEParams | None = None, fsr: FSRParams | None = None,
+                 workspace: torch.Tensor | None = None):
+        if not frames:
+            raise RfsrError("Batch: no frames")
+        self.frames = list(frames)
+        self.me = me or MEParams()
+        self.fsr = fsr or FSRParams()
+        self.n = len(self.frames)
+        self.device = self.frames[0].cur.device
+        self.descs = (FrameDesc * self.n)(*[_frame_desc(f, i) for i, f in enumerate(self.frames)])
+        self._mc, self._fc = self.me.c(), self.fsr.c()
+        L = lib()
+        need = L.rfsr_batch_workspace_bytes(self.descs, self.n, ctypes.byref(self._mc), ctypes.byref(self._fc))
+        if need == 0:
+            raise RfsrError("Batch: invalid frame descriptors")
+        if workspace is None:
+            workspace = torch.empty(int(need), dtype=torch.uint8, device=self.device)
+        if workspace.numel() < need or workspace.data_ptr() % 256 or workspace.device != self.device:
+            raise RfsrError(f"Batch: workspace needs {need} bytes on {self.device}, 256-byte aligned")
+        self.workspace = workspace
+        tb = int(L.rfsr_batch_table_bytes(self.descs, self.n))
+        image = torch.empty(tb, dtype=torch.uint8, pin_memory=True)
+        _check(L.rfsr_batch_write_tables(self.descs, self.n, ctypes.byref(self._mc), _ptr(workspace),
+                                         _ptr(image), tb), "rfsr_batch_write_tables")
+        self.tables = torch.empty(tb, dtype=torch.uint8, device=self.device)
+        if self.tables.data_ptr() % 256:
+            raise RfsrError("Batch: job-table allocation is not 256-byte aligned")
+        self.tables.copy_(image)
+        torch.cuda.current_stream(self.device).synchronize()
+
+    @staticmethod
+    def workspace_bytes(frames, me: MEParams | None = None, fsr: FSRParams | None = None) -> int:
+        descs = (FrameDesc * len(frames))(*[_frame_desc(f, i) for i, f in enumerate(frames)])
+        mc, fc = (me or MEParams()).c(), (fsr or FSRParams()).c()
+        n = lib().rfsr_batch_workspace_bytes(descs, len(frames), ctypes.byref(mc), ctypes.byref(fc))
+        if n == 0:
+            raise RfsrError("invalid frame descriptors")
+        return int(n)
+
+    def run(self, stage_events=None, stream=None):
+        ev = None
+        if stage_events is not None:
+            ev = (ctypes.c_void_p * 4)(*[e.handle for e in stage_events])
+        st = lib().rfsr_reconstruct_batch(self.descs, self.n, ctypes.byref(self._mc), ctypes.byref(self._fc),
+                                          _ptr(self.tables), ev, _ptr(self.workspace), self.workspace.numel(),
+                                          _stream(stream))
+        _check(st, "rfsr_reconstruct_batch")
+        return [(f.out, f.out_u8) for f in self.frames]
+
+    def capture(self):
+        """Record the chain in a graph (torch.cuda.CUDAGraph); replay() reruns it."""
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.graph(g):
+            self.run()
+        torch.cuda.synchronize(self.device)
+        return g
+
+
+class StreamSet:
+    """Many independent quarter-sampled streams, each its own causal
+    recursion with up to three references (Sec. 2.2), advanced one time step
+    at a time as ONE batch.  Frame sizes may differ between streams.
+
+    Each stream keeps a ring of four slots (measured frame, mask, outputs);
+    time step t writes slot t mod 4 and references slots t-1..t-3.  The
+    buffer pattern repeats every four steps, so from t = 3 on the chain of
+    each phase is captured once in a graph and replayed (graphs=True).
+    """
+
+    SLOTS = 4
+
+    def __init__(self, sizes, me: MEParams | None = None, fsr: FSRParams | None = None,
+                 nref: int = 3, graphs: bool = True, device=None):
+        if not 0 <= nref <= 3:
+            raise RfsrError("nref must be in 0..3")
+        self.sizes = [tuple(map(int, s)) for s in sizes]
+        self.me = me or MEParams()
+        self.fsr = fsr or FSRParams()
+        self.nref = nref
+        self.graphs = graphs
+        self.device = device or torch.device("cuda")
+        dev = self.device
+        mk = lambda H, W, dt: [torch.empty((H, W), dtype=dt, device=dev) for _ in range(self.SLOTS)]
+        self.meas = [mk(H, W, torch.uint8) for H, W in self.sizes]
+        self.mask = [mk(H, W, torch.uint8) for H, W in self.sizes]
+        self.out = [mk(H, W, torch.float32) for H, W in self.sizes]
+        self.out_u8 = [mk(H, W, torch.uint8) for H, W in self.sizes]
+        self.t = 0
+        self._batches = {}
+        self._graphs = {}
+        # one workspace for every phase (phases never overlap)
+        need = max(Batch.workspace_bytes(self._frames(slot, self.nref), self.me, self.fsr)
+                   for slot in range(self.SLOTS))
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+
+    def _frames(self, slot, nref):
+        fr = []
+        for s in range(len(self.sizes)):
+            refs = tuple((self.out_u8[s][(slot - k) % self.SLOTS], self.meas[s][(slot - k) % self.SLOTS],
+                          self.mask[s][(slot - k) % self.SLOTS]) for k in range(1, nref + 1))
+            fr.append(BatchFrame(self.meas[s][slot], self.mask[s][slot], refs, self.out[s][slot],
+                                 self.out_u8[s][slot]))
+        return fr
+
+    def step(self, meas, masks, stage_events=None):
+        """Reconstruct one frame of every stream.  meas/masks: sequences of
+        uint8 (H, W) device tensors, one per stream.  Returns the list of
+        (out float32, out_u8 uint8) planes (valid until the same slot is
+        written again, four steps later)."""
+        if len(meas) != len(self.sizes) or len(masks) != len(self.sizes):
+            raise RfsrError("StreamSet.step: one frame and mask per stream")
+        slot = self.t % self.SLOTS
+        nref = min(self.t, self.nref)
+        for s in range(len(self.sizes)):
+            self.meas[s][slot].copy_(meas[s], non_blocking=True)
+            self.mask[s][slot].copy_(masks[s], non_blocking=True)
+        key = (slot, nref)
+        b = self._batches.get(key)
+        if b is None:
+            b = self._batches[key] = Batch(self._frames(slot, nref), self.me, self.fsr, self.workspace)
+        if self.graphs and nref == self.nref and stage_events is None:
+            g = self._graphs.get(key)
+            if g is None:
+                g = self._graphs[key] = b.capture()
+            g.replay()
+        else:
+            b.run(stage_events=stage_events)
+        self.t += 1
+        return [(self.out[s][slot], self.out_u8[s][slot]) for s in range(len(self.sizes))]

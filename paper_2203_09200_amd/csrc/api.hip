@@ -1,9 +1,12 @@
-// C ABI of librfsr: argument validation, workspace layout, stage sequencing.
-// Every step of the reconstruction runs in the kernels of fsr.hip and
-// motion.hip; this file only validates, carves the caller's workspace and
-// enqueues launches on the caller's stream.
+// C ABI of librfsr: argument validation, workspace layout, job construction
+// and stage sequencing.  Every step of the reconstruction runs in the kernels
+// of fsr.hip and motion.hip; this file only validates, carves the caller's
+// workspace, builds the jobs the kernels read and enqueues launches on the
+// caller's stream.
 #include <math.h>
 #include <string.h>
+
+#include <vector>
 
 #include "common.h"
 
@@ -11,7 +14,8 @@ using namespace rfsr;
 
 namespace {
 
-constexpr int32_t kVersion = 10000;   // 1.0.0
+constexpr int32_t kVersion = 10100;   // 1.1.0
+constexpr int kMaxBatch = 4096;
 
 rfsr_status from_hip(hipError_t e) { return e == hipSuccess ? RFSR_OK : RFSR_EDEVICE; }
 
@@ -49,25 +53,250 @@ rfsr_status check_ws(void* ws, size_t have, size_t need) {
     return RFSR_OK;
 }
 
-// Frame workspace: FSR tables | motion scratch | per reference (mv_a, mv_b,
-// accept) | FSR input values (f32) and classes (u8).  Planes use pitch W.
-struct FrameLayout {
-    size_t tables, motion, ref[3][3], values, cls, total;
-    FrameLayout(int H, int W, int nref, const rfsr_me_params& me) {
+// Scratch of one frame, as offsets from the frame's base (planes of pitch W):
+// n map, window plane, FSR input, and per reference the vectors, decisions,
+// best forward cost, medians and reverse field.
+struct FrameScratch {
+    size_t nmap, fm, values, cls;
+    size_t mv_a[3], mv_b[3], acc[3], cost[3], ma[3], mb[3], ra[3], rb[3];
+    size_t bytes;
+    FrameScratch(int H, int W, int nref) {
         const size_t px = (size_t)H * W;
         size_t o = 0;
-        tables = o; o = align256(o + sizeof(FsrTables));
-        motion = o; o = align256(o + motion_ws_bytes(H, W, me));
-        for (int k = 0; k < 3; ++k)
-            for (int j = 0; j < 3; ++j) {
-                ref[k][j] = o;
-                if (k < nref) o = align256(o + px);
-            }
+        nmap = o; o = align256(o + px);
+        fm = o; o = align256(o + sizeof(uint2) * (size_t)(H + 2 * kPad) * (W + 2 * kPad));
         values = o; o = align256(o + 4 * px);
         cls = o; o = align256(o + px);
+        for (int k = 0; k < 3; ++k) {
+            const size_t n = k < nref ? px : 0;
+            mv_a[k] = o; o = align256(o + n);
+            mv_b[k] = o; o = align256(o + n);
+            acc[k] = o; o = align256(o + n);
+            cost[k] = o; o = align256(o + 2 * n);
+            ma[k] = o; o = align256(o + n);
+            mb[k] = o; o = align256(o + n);
+            ra[k] = o; o = align256(o + n);
+            rb[k] = o; o = align256(o + n);
+        }
+        bytes = o;
+    }
+};
+
+// Workspace of the single-frame entry points: FSR tables | frame scratch.
+size_t single_ws(int H, int W, int nref) {
+    return align256(sizeof(FsrTables)) + FrameScratch(H, W, nref).bytes;
+}
+
+// One frame to reconstruct; rfsr_frame_desc and the single-frame arguments
+// both become one of these.
+struct Frame {
+    const uint8_t* cur;
+    const uint8_t* cur_mask;
+    const uint8_t* ref_recon[3];
+    const uint8_t* ref_meas[3];
+    const uint8_t* ref_mask[3];
+    float* out;
+    uint8_t* out_u8;
+    int nref, H, W;
+    int64_t pitch;
+};
+
+rfsr_status check_frame(const Frame& f) {
+    if (!f.cur || !f.cur_mask || !f.out) return RFSR_EINVAL;
+    if (f.nref < 0 || f.nref > 3) return RFSR_EINVAL;
+    for (int k = 0; k < f.nref; ++k)
+        if (!f.ref_recon[k] || !f.ref_meas[k] || !f.ref_mask[k]) return RFSR_EINVAL;
+    return check_shape(f.H, f.W, f.pitch);
+}
+
+// The frame job and the nref reference jobs of `f`, whose scratch starts at
+// `base`.  The reverse tests of the frame path run only on projectable pixels
+// (ref_mask set).  First-workgroup offsets are left at 0.
+void make_jobs(const Frame& f, uint8_t* base, bool windows, FrameJob& fj, RefJob* rj) {
+    const FrameScratch L(f.H, f.W, f.nref);
+    memset(&fj, 0, sizeof(fj));
+    fj.cur = f.cur;
+    fj.cur_mask = f.cur_mask;
+    fj.fm = windows ? reinterpret_cast<uint2*>(base + L.fm) : nullptr;
+    fj.values = reinterpret_cast<float*>(base + L.values);
+    fj.cls = base + L.cls;
+    fj.out = f.out;
+    fj.out_u8 = f.out_u8;
+    fj.pitch = f.pitch;
+    fj.opitch = f.W;
+    fj.vpitch = f.W;
+    fj.H = f.H;
+    fj.W = f.W;
+    fj.nref = f.nref;
+    for (int k = 0; k < f.nref; ++k) {
+        RefJob& j = rj[k];
+        memset(&j, 0, sizeof(j));
+        j.cur = f.cur;
+        j.cur_mask = f.cur_mask;
+        j.ref = f.ref_recon[k];
+        j.ref_mask = f.ref_mask[k];
+        j.mv_a = reinterpret_cast<int8_t*>(base + L.mv_a[k]);
+        j.mv_b = reinterpret_cast<int8_t*>(base + L.mv_b[k]);
+        j.accept = base + L.acc[k];
+        j.cost = reinterpret_cast<uint16_t*>(base + L.cost[k]);
+        j.nmap_w = k == 0 ? base + L.nmap : nullptr;   // n depends on the frame only
+        j.nmap = base + L.nmap;
+        j.fm = reinterpret_cast<const uint2*>(base + L.fm);
+        j.ma = reinterpret_cast<int8_t*>(base + L.ma[k]);
+        j.mb = reinterpret_cast<int8_t*>(base + L.mb[k]);
+        j.ra = reinterpret_cast<int8_t*>(base + L.ra[k]);
+        j.rb = reinterpret_cast<int8_t*>(base + L.rb[k]);
+        j.pitch = f.pitch;
+        j.opitch = f.W;
+        j.cpitch = f.W;
+        j.H = f.H;
+        j.W = f.W;
+        fj.mv_a[k] = j.mv_a;
+        fj.mv_b[k] = j.mv_b;
+        fj.accept[k] = j.accept;
+        fj.ref_meas[k] = f.ref_meas[k];
+        fj.ref_mask[k] = f.ref_mask[k];
+    }
+}
+
+template <class J>
+Jobs<J> single(const J& j) {
+    Jobs<J> js;
+    js.table = nullptr;
+    js.n = 0;
+    js.one = j;
+    return js;
+}
+
+template <class J>
+Jobs<J> table(const uint8_t* image, size_t offset, int n, unsigned long long key) {
+    Jobs<J> js;
+    memset(&js, 0, sizeof(js));
+    js.table = reinterpret_cast<const J*>(image + offset);
+    js.stamp = reinterpret_cast<const unsigned long long*>(image);
+    js.key = key;
+    js.n = n;
+    return js;
+}
+
+// ------------------------------------------------------------------ batch --
+Frame to_frame(const rfsr_frame_desc& d) {
+    Frame f;
+    f.cur = d.cur;
+    f.cur_mask = d.cur_mask;
+    for (int k = 0; k < 3; ++k) {
+        f.ref_recon[k] = d.ref_recon[k];
+        f.ref_meas[k] = d.ref_meas[k];
+        f.ref_mask[k] = d.ref_mask[k];
+    }
+    f.out = d.out;
+    f.out_u8 = d.out_u8;
+    f.nref = d.nref;
+    f.H = d.H;
+    f.W = d.W;
+    f.pitch = d.pitch;
+    return f;
+}
+
+rfsr_status check_batch(const rfsr_frame_desc* d, int n) {
+    if (!d || n <= 0 || n > kMaxBatch) return RFSR_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const rfsr_status st = check_frame(to_frame(d[i]));
+        if (st != RFSR_OK) return st;
+    }
+    return RFSR_OK;
+}
+
+// Workspace of a batch: FSR tables | scratch of frame 0 | frame 1 | ...
+// Job-table image: header | FrameJob[n] | RefJob[total references].
+struct BatchLayout {
+    int nrefs = 0;
+    size_t table_bytes, refs_offset, total;
+    std::vector<size_t> frame_base;
+    BatchLayout(const rfsr_frame_desc* d, int n) : frame_base(n) {
+        for (int i = 0; i < n; ++i) nrefs += d[i].nref;
+        refs_offset = kTableHeader + sizeof(FrameJob) * (size_t)n;
+        table_bytes = align256(refs_offset + sizeof(RefJob) * (size_t)nrefs);
+        size_t o = align256(sizeof(FsrTables));
+        for (int i = 0; i < n; ++i) {
+            frame_base[i] = o;
+            o += FrameScratch(d[i].H, d[i].W, d[i].nref).bytes;
+        }
         total = o;
     }
 };
+
+// FNV-1a over the descriptors, the check and the workspace address: the
+// table image is valid exactly for this combination.
+unsigned long long batch_key(const rfsr_frame_desc* d, int n, int check, const void* ws) {
+    unsigned long long h = 1469598103934665603ull;
+    auto mix = [&h](const void* p, size_t len) {
+        const uint8_t* b = static_cast<const uint8_t*>(p);
+        for (size_t i = 0; i < len; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(ws);
+    mix(&n, sizeof(n));
+    mix(&check, sizeof(check));
+    mix(&addr, sizeof(addr));
+    for (int i = 0; i < n; ++i) {
+        // hash the fields, not the struct bytes (reserved / padding ignored)
+        mix(&d[i].cur, sizeof(d[i].cur));
+        mix(&d[i].cur_mask, sizeof(d[i].cur_mask));
+        for (int k = 0; k < 3; ++k) {
+            const bool used = k < d[i].nref;
+            const void* p3[3] = {used ? d[i].ref_recon[k] : nullptr, used ? d[i].ref_meas[k] : nullptr,
+                                 used ? d[i].ref_mask[k] : nullptr};
+            mix(p3, sizeof(p3));
+        }
+        mix(&d[i].out, sizeof(d[i].out));
+        mix(&d[i].out_u8, sizeof(d[i].out_u8));
+        mix(&d[i].nref, sizeof(d[i].nref));
+        mix(&d[i].H, sizeof(d[i].H));
+        mix(&d[i].W, sizeof(d[i].W));
+        mix(&d[i].pitch, sizeof(d[i].pitch));
+    }
+    return h;
+}
+
+// Jobs of a batch with their first-workgroup offsets in the merged grids.
+struct BatchPlan {
+    std::vector<FrameJob> frames;
+    std::vector<RefJob> refs;
+    int win = 0, tiles = 0, px_refs = 0, frmc = 0, px_frames = 0, blocks = 0;
+};
+
+BatchPlan plan_batch(const rfsr_frame_desc* d, int n, const rfsr_me_params& me, uint8_t* ws,
+                     const BatchLayout& L) {
+    BatchPlan p;
+    p.frames.resize(n);
+    p.refs.reserve(L.nrefs);
+    for (int i = 0; i < n; ++i) {
+        const Frame f = to_frame(d[i]);
+        const bool windows = f.nref > 0 && check_needs_windows(me.check);
+        RefJob rj[3];
+        FrameJob& fj = p.frames[i];
+        make_jobs(f, ws + L.frame_base[i], windows, fj, rj);
+        fj.g_px = p.px_frames;
+        fj.g_win = p.win;
+        fj.g_blk = p.blocks;
+        p.px_frames += px_groups(f.H, f.W);
+        p.win += windows ? win_groups(f.H, f.W) : 0;
+        p.blocks += (f.H / kBlock) * (f.W / kBlock);
+        for (int k = 0; k < f.nref; ++k) {
+            rj[k].g_tile = p.tiles;
+            rj[k].g_px = p.px_refs;
+            rj[k].g_frmc = p.frmc;
+            p.tiles += me_tiles(f.H, f.W);
+            p.px_refs += px_groups(f.H, f.W);
+            p.frmc += frmc_groups(f.H, f.W);
+            p.refs.push_back(rj[k]);
+        }
+    }
+    return p;
+}
 
 }  // namespace
 
@@ -76,10 +305,9 @@ extern "C" {
 size_t rfsr_workspace_bytes(int32_t H, int32_t W, int32_t nref, const rfsr_me_params* me,
                             const rfsr_fsr_params* fsr) {
     if (check_shape(H, W, W) != RFSR_OK || nref < 0 || nref > 3) return 0;
-    rfsr_me_params mp = me ? *me : rfsr_me_params{4, 9, RFSR_CHECK_NNC_FRMC, 0};
     if (me && check_me(me) == RFSR_EINVAL) return 0;
     if (fsr && check_fsr(fsr) == RFSR_EINVAL) return 0;
-    return FrameLayout(H, W, nref, mp).total;
+    return single_ws(H, W, nref > 0 ? nref : 1);
 }
 
 rfsr_status rfsr_motion_check(const uint8_t* cur, const uint8_t* cur_mask, const uint8_t* ref_recon,
@@ -91,12 +319,36 @@ rfsr_status rfsr_motion_check(const uint8_t* cur, const uint8_t* cur_mask, const
     rfsr_status st = check_shape(H, W, pitch);
     if (st != RFSR_OK) return st;
     if ((st = check_me(me)) != RFSR_OK) return st;
-    const size_t need = motion_ws_bytes(H, W, *me);
-    if ((st = check_ws(workspace, ws_bytes, need)) != RFSR_OK) return st;
+    if ((st = check_ws(workspace, ws_bytes, single_ws(H, W, 1))) != RFSR_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int8_t* mv_b = mv + (int64_t)H * pitch;
-    return from_hip(run_motion_check(cur, cur_mask, ref_recon, H, W, pitch, *me, mv, mv_b, pitch, accept,
-                                     pitch, cost, pitch, counters, workspace, false, nullptr, s));
+    uint8_t* base = static_cast<uint8_t*>(workspace) + align256(sizeof(FsrTables));
+    Frame f;
+    memset(&f, 0, sizeof(f));
+    f.cur = cur;
+    f.cur_mask = cur_mask;
+    f.ref_recon[0] = ref_recon;
+    f.nref = 1;
+    f.H = H;
+    f.W = W;
+    f.pitch = pitch;
+    FrameJob fj;
+    RefJob rj[3];
+    const bool windows = check_needs_windows(me->check);
+    make_jobs(f, base, windows, fj, rj);
+    RefJob& j = rj[0];
+    j.ref_mask = nullptr;   // decide every pixel
+    j.mv_a = mv;            // outputs in the caller's planes (pitch)
+    j.mv_b = mv + (int64_t)H * pitch;
+    j.accept = accept;
+    j.opitch = pitch;
+    if (cost) {
+        j.cost = cost;
+        j.cpitch = pitch;
+    }
+    hipError_t e = launch_windows(single(fj), windows ? win_groups(H, W) : 0, s);
+    if (e == hipSuccess)
+        e = launch_motion(single(j), me_tiles(H, W), px_groups(H, W), frmc_groups(H, W), *me, counters, s);
+    return from_hip(e);
 }
 
 rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32_t W, int64_t pitch,
@@ -109,8 +361,19 @@ rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32
     if ((st = check_ws(workspace, ws_bytes, align256(sizeof(FsrTables)))) != RFSR_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     FsrTables* tab = static_cast<FsrTables*>(workspace);
+    FrameJob fj;
+    memset(&fj, 0, sizeof(fj));
+    fj.values = const_cast<float*>(values);   // read only by the FSR kernel
+    fj.cls = const_cast<uint8_t*>(cls);
+    fj.out = out;
+    fj.out_u8 = out_u8;
+    fj.pitch = pitch;
+    fj.opitch = pitch;
+    fj.vpitch = pitch;
+    fj.H = H;
+    fj.W = W;
     hipError_t e = launch_fsr_tables(tab, fsr->rho, s);
-    if (e == hipSuccess) e = launch_fsr(values, cls, H, W, pitch, *fsr, tab, out, out_u8, pitch, s);
+    if (e == hipSuccess) e = launch_fsr(single(fj), (H / kBlock) * (W / kBlock), *fsr, tab, s);
     return from_hip(e);
 }
 
@@ -121,48 +384,128 @@ rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, 
                                    const rfsr_fsr_params* fsr, float* out, uint8_t* out_u8,
                                    void* const* stage_events, void* workspace, size_t ws_bytes,
                                    void* stream) {
-    if (!cur || !cur_mask || !out) return RFSR_EINVAL;
     if (nref < 0 || nref > 3) return RFSR_EINVAL;
-    if (nref > 0) {
-        if (!ref_recon || !ref_meas || !ref_mask) return RFSR_EINVAL;
-        for (int k = 0; k < nref; ++k)
-            if (!ref_recon[k] || !ref_meas[k] || !ref_mask[k]) return RFSR_EINVAL;
-    }
+    if (nref > 0 && (!ref_recon || !ref_meas || !ref_mask)) return RFSR_EINVAL;
     if (stage_events)
         for (int k = 0; k < 4; ++k)
             if (!stage_events[k]) return RFSR_EINVAL;
-    rfsr_status st = check_shape(H, W, pitch);
+    Frame f;
+    memset(&f, 0, sizeof(f));
+    f.cur = cur;
+    f.cur_mask = cur_mask;
+    for (int k = 0; k < nref; ++k) {
+        f.ref_recon[k] = ref_recon[k];
+        f.ref_meas[k] = ref_meas[k];
+        f.ref_mask[k] = ref_mask[k];
+    }
+    f.out = out;
+    f.out_u8 = out_u8;
+    f.nref = nref;
+    f.H = H;
+    f.W = W;
+    f.pitch = pitch;
+    rfsr_status st = check_frame(f);
     if (st != RFSR_OK) return st;
     if ((st = check_me(me)) != RFSR_OK) return st;
     if ((st = check_fsr(fsr)) != RFSR_OK) return st;
-    const FrameLayout L(H, W, nref, *me);
-    if ((st = check_ws(workspace, ws_bytes, L.total)) != RFSR_OK) return st;
+    if ((st = check_ws(workspace, ws_bytes, single_ws(H, W, nref > 0 ? nref : 1))) != RFSR_OK) return st;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
-    uint8_t* base = static_cast<uint8_t*>(workspace);
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    FsrTables* tab = reinterpret_cast<FsrTables*>(ws);
+    const bool windows = nref > 0 && check_needs_windows(me->check);
+    FrameJob fj;
+    RefJob rj[3];
+    make_jobs(f, ws + align256(sizeof(FsrTables)), windows, fj, rj);
     hipError_t e = hipSuccess;
     auto record = [&](int k) {
         if (stage_events && e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s);
     };
     record(0);
-    FsrTables* tab = reinterpret_cast<FsrTables*>(base + L.tables);
     if (e == hipSuccess) e = launch_fsr_tables(tab, fsr->rho, s);
-    ProjRef refs[3];
-    for (int k = 0; k < nref && e == hipSuccess; ++k) {
-        int8_t* a = reinterpret_cast<int8_t*>(base + L.ref[k][0]);
-        int8_t* b = reinterpret_cast<int8_t*>(base + L.ref[k][1]);
-        uint8_t* acc = base + L.ref[k][2];
-        e = run_motion_check(cur, cur_mask, ref_recon[k], H, W, pitch, *me, a, b, W, acc, W, nullptr, 0,
-                             nullptr, base + L.motion, k > 0, ref_mask[k], s);
-        refs[k] = ProjRef{a, b, acc, ref_meas[k], ref_mask[k]};
+    if (e == hipSuccess && windows) e = launch_windows(single(fj), win_groups(H, W), s);
+    for (int k = 0; k < nref && e == hipSuccess; ++k)
+        e = launch_motion(single(rj[k]), me_tiles(H, W), px_groups(H, W), frmc_groups(H, W), *me, nullptr, s);
+    record(1);
+    if (e == hipSuccess) e = launch_project(single(fj), px_groups(H, W), s);
+    record(2);
+    if (e == hipSuccess) e = launch_fsr(single(fj), (H / kBlock) * (W / kBlock), *fsr, tab, s);
+    record(3);
+    return from_hip(e);
+}
+
+size_t rfsr_batch_workspace_bytes(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
+                                  const rfsr_fsr_params* fsr) {
+    if (check_batch(frames, n) != RFSR_OK) return 0;
+    if (me && check_me(me) == RFSR_EINVAL) return 0;
+    if (fsr && check_fsr(fsr) == RFSR_EINVAL) return 0;
+    return BatchLayout(frames, n).total;
+}
+
+size_t rfsr_batch_table_bytes(const rfsr_frame_desc* frames, int32_t n) {
+    if (check_batch(frames, n) != RFSR_OK) return 0;
+    return BatchLayout(frames, n).table_bytes;
+}
+
+rfsr_status rfsr_batch_write_tables(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
+                                    const void* workspace, void* image, size_t image_bytes) {
+    rfsr_status st = check_batch(frames, n);
+    if (st != RFSR_OK) return st;
+    if ((st = check_me(me)) != RFSR_OK) return st;
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0) return RFSR_EWORKSPACE;
+    const BatchLayout L(frames, n);
+    if (!image || image_bytes < L.table_bytes) return RFSR_EINVAL;
+    const BatchPlan p = plan_batch(frames, n, *me, static_cast<uint8_t*>(const_cast<void*>(workspace)), L);
+    uint8_t* img = static_cast<uint8_t*>(image);
+    memset(img, 0, L.table_bytes);
+    TableHeader hdr;
+    memset(&hdr, 0, sizeof(hdr));
+    hdr.key = batch_key(frames, n, me->check, workspace);
+    hdr.n_frames = n;
+    hdr.n_refs = (int)p.refs.size();
+    memcpy(img, &hdr, sizeof(hdr));
+    memcpy(img + kTableHeader, p.frames.data(), sizeof(FrameJob) * p.frames.size());
+    if (!p.refs.empty()) memcpy(img + L.refs_offset, p.refs.data(), sizeof(RefJob) * p.refs.size());
+    return RFSR_OK;
+}
+
+rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
+                                   const rfsr_fsr_params* fsr, const void* job_tables,
+                                   void* const* stage_events, void* workspace, size_t ws_bytes,
+                                   void* stream) {
+    rfsr_status st = check_batch(frames, n);
+    if (st != RFSR_OK) return st;
+    if ((st = check_me(me)) != RFSR_OK) return st;
+    if ((st = check_fsr(fsr)) != RFSR_OK) return st;
+    if (!job_tables || ((uintptr_t)job_tables & 255u) != 0) return RFSR_EINVAL;
+    if (stage_events)
+        for (int k = 0; k < 4; ++k)
+            if (!stage_events[k]) return RFSR_EINVAL;
+    const BatchLayout L(frames, n);
+    if ((st = check_ws(workspace, ws_bytes, L.total)) != RFSR_OK) return st;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    const BatchPlan p = plan_batch(frames, n, *me, ws, L);   // grid sizes
+    const unsigned long long key = batch_key(frames, n, me->check, workspace);
+    const uint8_t* img = static_cast<const uint8_t*>(job_tables);
+    const Jobs<FrameJob> jf = table<FrameJob>(img, kTableHeader, n, key);
+    const Jobs<RefJob> jr = table<RefJob>(img, L.refs_offset, (int)p.refs.size(), key);
+    FsrTables* tab = reinterpret_cast<FsrTables*>(ws);
+    hipError_t e = hipSuccess;
+    auto record = [&](int k) {
+        if (stage_events && e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s);
+    };
+    record(0);
+    if (e == hipSuccess) e = launch_fsr_tables(tab, fsr->rho, s);
+    if (e == hipSuccess && !p.refs.empty()) {
+        e = launch_windows(jf, p.win, s);
+        if (e == hipSuccess) e = launch_motion(jr, p.tiles, p.px_refs, p.frmc, *me, nullptr, s);
     }
     record(1);
-    float* values = reinterpret_cast<float*>(base + L.values);
-    uint8_t* cls = base + L.cls;
-    if (e == hipSuccess) e = launch_project(cur, cur_mask, H, W, pitch, nref, refs, W, values, cls, s);
+    if (e == hipSuccess) e = launch_project(jf, p.px_frames, s);
     record(2);
-    // FSR reads values/cls (workspace, pitch W) and writes with the caller's pitch.
-    if (e == hipSuccess) e = launch_fsr(values, cls, H, W, W, *fsr, tab, out, out_u8, pitch, s);
+    if (e == hipSuccess) e = launch_fsr(jf, p.blocks, *fsr, tab, s);
     record(3);
     return from_hip(e);
 }

@@ -77,37 +77,134 @@ struct FsrTables {
     double tw[2 * kSupport];          // exp(-2 pi i t / 32), t = 0..31, (re, im)
 };
 
+// ------------------------------------------------------------------- jobs --
+// Every kernel reads its frame or (frame, reference) pair from a job.  A
+// single frame passes its jobs by value (`one`); a batch of frames passes a
+// device table and each workgroup finds its job from the first-workgroup
+// offsets stored in the entries (entries sorted by offset).  A batch table
+// image starts with a header whose key hashes the descriptors it was built
+// from; a kernel handed an image whose key differs from the launch's key
+// gets an empty job (H = W = 0) and returns without touching memory.
+
+struct TableHeader {
+    unsigned long long key;
+    int n_frames;
+    int n_refs;
+};
+constexpr size_t kTableHeader = 256;
+
+// One (frame, reference) pair of the motion path.
+struct RefJob {
+    const uint8_t* cur;        // measured current frame (pitch)
+    const uint8_t* cur_mask;   // its mask (pitch)
+    const uint8_t* ref;        // reconstruction of the reference frame (pitch)
+    const uint8_t* ref_mask;   // mask of the reference, or nullptr: with it the reverse
+                               // tests run only where the pixel is projectable
+    int8_t* mv_a;              // outputs (opitch)
+    int8_t* mv_b;
+    uint8_t* accept;
+    uint16_t* cost;            // best forward cost (cpitch); read by RMC/FRMC
+    uint8_t* nmap_w;           // n map to write (pitch W), or nullptr
+    const uint8_t* nmap;       // the frame's n map (pitch W)
+    const uint2* fm;           // the frame's window plane
+    int8_t* ma;                // scratch (pitch W): medians, reverse field
+    int8_t* mb;
+    int8_t* ra;
+    int8_t* rb;
+    int64_t pitch;
+    int64_t opitch;
+    int64_t cpitch;
+    int H, W;
+    int g_tile;                // first workgroup in the ME tile grid
+    int g_px;                  // first workgroup in the 256-pixel grid
+    int g_frmc;                // first workgroup in the FRMC-run grid
+};
+
+// One frame: window plane, projection, FSR.
+struct FrameJob {
+    const uint8_t* cur;
+    const uint8_t* cur_mask;
+    const int8_t* mv_a[3];     // per reference (opitch)
+    const int8_t* mv_b[3];
+    const uint8_t* accept[3];
+    const uint8_t* ref_meas[3];
+    const uint8_t* ref_mask[3];
+    uint2* fm;                 // window plane to build, or nullptr
+    float* values;             // FSR input (vpitch)
+    uint8_t* cls;
+    float* out;                // outputs (pitch)
+    uint8_t* out_u8;           // nullable
+    int64_t pitch;
+    int64_t opitch;
+    int64_t vpitch;
+    int H, W;
+    int nref;
+    int g_px;                  // first workgroup in the 256-pixel grid
+    int g_win;                 // first workgroup in the window-plane grid
+    int g_blk;                 // first FSR block
+};
+
+template <class J>
+struct Jobs {
+    const J* table;                     // device table, or nullptr
+    const unsigned long long* stamp;    // key stored in the table's image
+    unsigned long long key;             // key expected by this launch
+    int n;                              // entries in `table`; 0 selects `one`
+    J one;                              // the single job; all zero with a table
+};
+
+// Tables are read through the constant address space: the job index is
+// wave-uniform, so every field arrives by scalar loads and the pointers in it
+// stay in SGPRs (generic pointers would turn every access that depends on the
+// job into a flat access).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+#else   // the host pass only parses device code
+template <class T>
+using const_ptr = const T*;
+#endif
+
+template <class J>
+__device__ __forceinline__ J job_at(const Jobs<J>& js, int g, int J::*base) {
+    // a batch launch carries an all-zero `one`: the empty job for a stale image
+    if (js.n == 0) return js.one;
+    if (*(const_ptr<unsigned long long>)(uintptr_t)js.stamp != js.key) return js.one;
+    const_ptr<J> t = (const_ptr<J>)(uintptr_t)js.table;
+    int lo = 0, hi = js.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t[mid].*base <= g) lo = mid; else hi = mid - 1;
+    }
+    return t[lo];
+}
+
+constexpr int kPad = 16;         // border of the window planes
+constexpr int kMeTile = 16;      // forward ME tile edge
+constexpr int kFrmcRun = 2048;   // pixels per FRMC workgroup (cascade)
+
+__host__ __device__ inline int me_tiles(int H, int W) {
+    return ((W + kMeTile - 1) / kMeTile) * ((H + kMeTile - 1) / kMeTile);
+}
+__host__ __device__ inline int px_groups(int H, int W) { return (H * W + 255) / 256; }
+__host__ __device__ inline int win_groups(int H, int W) { return ((H + 2 * kPad) * (W + 2 * kPad) + 255) / 256; }
+__host__ __device__ inline int frmc_groups(int H, int W) { return (H * W + kFrmcRun - 1) / kFrmcRun; }
+
 // --------------------------------------------------------------- launches --
 // Each returns hipSuccess or the launch error.
 hipError_t launch_fsr_tables(FsrTables* t, double rho, hipStream_t s);
-hipError_t launch_fsr(const float* values, const uint8_t* cls, int H, int W, int64_t pitch,
-                      const rfsr_fsr_params& p, const FsrTables* tables, float* out,
-                      uint8_t* out_u8, int64_t out_pitch, hipStream_t s);
+// FSR over all `total_blocks` blocks of the frames in `js`.
+hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
+                      const FsrTables* tables, hipStream_t s);
 
-struct MotionWs;   // defined in motion.hip
-size_t motion_ws_bytes(int H, int W, const rfsr_me_params& me);
-size_t frame_ws_bytes(int H, int W, int nref, const rfsr_me_params& me);
-
-// Forward ME + check of one reference.  ws: motion workspace of
-// motion_ws_bytes(); need (nullable, device H x W uint8, pitch W) restricts
-// the expensive reverse test to pixels where need != 0 (decision elsewhere 0).
-hipError_t run_motion_check(const uint8_t* cur, const uint8_t* cur_mask, const uint8_t* ref,
-                            int H, int W, int64_t pitch, const rfsr_me_params& me,
-                            int8_t* mv_a, int8_t* mv_b, int64_t mv_pitch, uint8_t* accept,
-                            int64_t acc_pitch, uint16_t* cost, int64_t cost_pitch,
-                            unsigned long long* counters, void* ws, bool windows_ready,
-                            const uint8_t* ref_mask_for_need, hipStream_t s);
-
-// Projection (Sec. 2.2) of up to 3 references into values/cls (pitch W).
-struct ProjRef {
-    const int8_t* mv_a;
-    const int8_t* mv_b;
-    const uint8_t* accept;
-    const uint8_t* meas;
-    const uint8_t* mask;
-};
-hipError_t launch_project(const uint8_t* cur, const uint8_t* cur_mask, int H, int W,
-                          int64_t pitch, int nref, const ProjRef* refs, int64_t ipitch,
-                          float* values, uint8_t* cls, hipStream_t s);
+// Window planes of the frames in `js` (frames with fm == nullptr skipped).
+hipError_t launch_windows(const Jobs<FrameJob>& js, int total_groups, hipStream_t s);
+// Projection (Sec. 2.2) of the frames in `js`.
+hipError_t launch_project(const Jobs<FrameJob>& js, int total_groups, hipStream_t s);
+// Forward ME and the consistency check of the (frame, reference) pairs in
+// `js` (window planes must exist when the check needs them).
+hipError_t launch_motion(const Jobs<RefJob>& js, int total_tiles, int total_px, int total_frmc,
+                         const rfsr_me_params& me, unsigned long long* counters, hipStream_t s);
+bool check_needs_windows(int check);
 
 }  // namespace rfsr

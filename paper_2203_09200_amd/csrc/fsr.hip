@@ -193,11 +193,12 @@ __global__ void fsr_tables_kernel(FsrTables* t, double rho) {
 
 // LDS (the 16 KB W table per block) caps residency at two waves per SIMD;
 // telling the compiler so lets it keep the LDS reads of an iteration in flight.
+// One workgroup per block of the flat block index over all the frames of
+// `js`.  (A loop over several blocks per workgroup lets the compiler hoist
+// per-lane tables out of it and spill; launches are cheap by comparison.)
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void fsr_block_kernel(
-    const float* __restrict__ values, const uint8_t* __restrict__ cls, int H, int W,
-    int64_t pitch, const FsrTables* __restrict__ tab, float* __restrict__ out,
-    uint8_t* __restrict__ out_u8, int64_t out_pitch, int K, double gamma, double projw,
-    int overwrite) {
+    Jobs<FrameJob> js, int total, const FsrTables* __restrict__ tab, int K, double gamma,
+    double projw, int overwrite) {
     // W table (32 x 32 complex double); the transpose planes reuse it.  Static,
     // so its LDS base folds into the read addresses.  The (bin, dlt) list of
     // K float4 entries is dynamic LDS.
@@ -206,10 +207,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     extern __shared__ float4 list[];
     uint8_t* smem = reinterpret_cast<uint8_t*>(s_T);
 
-    const int nbw = W >> 2;
-    const int nblk = nbw * (H >> 2);
-    const int blk = xcd_remap(blockIdx.x, nblk);
-    const int bi = blk / nbw, bj = blk - bi * nbw;
     const int lane = threadIdx.x;
     const int c = lane & 31, h = lane >> 5;
     const double* __restrict__ tw = tab->tw;
@@ -219,154 +216,169 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         s_tw[2 * lane + 1] = tw[2 * lane + 1];
     }
 
-    // 1. gather: lane (h, c) holds support rows m = i + 16 h of column c.
-    //    Loads use clamped coordinates (always in bounds); positions outside
-    //    the frame get weight 0.
-    double zr[16], zi[16];
+    const int gb = xcd_remap(blockIdx.x, total);
     {
-        const int y0 = 4 * bi - 14, x = 4 * bj - 14 + c;
-        const bool xin = (unsigned)x < (unsigned)W;
-        const int xc = min(max(x, 0), W - 1);
+        const FrameJob fj = job_at(js, gb, &FrameJob::g_blk);
+        if (fj.H == 0) return;   // empty job (stale batch table)
+        const int H = fj.H, W = fj.W;
+        const int64_t pitch = fj.vpitch, out_pitch = fj.pitch;
+        const float* __restrict__ values = fj.values;
+        const uint8_t* __restrict__ cls = fj.cls;
+        float* __restrict__ out = fj.out;
+        uint8_t* __restrict__ out_u8 = fj.out_u8;
+        const int nbw = W >> 2;
+        const int blk = gb - fj.g_blk;
+        const int bi = blk / nbw, bj = blk - bi * nbw;
+
+        // 1. gather: lane (h, c) holds support rows m = i + 16 h of column c.
+        //    Loads use clamped coordinates (always in bounds); positions outside
+        //    the frame get weight 0.
+        double zr[16], zi[16];
+        {
+            const int y0 = 4 * bi - 14, x = 4 * bj - 14 + c;
+            const bool xin = (unsigned)x < (unsigned)W;
+            const int xc = min(max(x, 0), W - 1);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int m = i + 16 * h;
-            const int y = y0 + m;
-            const bool in = xin && (unsigned)y < (unsigned)H;
-            const int64_t off = (int64_t)min(max(y, 0), H - 1) * pitch + xc;
+            for (int i = 0; i < 16; ++i) {
+                const int m = i + 16 * h;
+                const int y = y0 + m;
+                const bool in = xin && (unsigned)y < (unsigned)H;
+                const int64_t off = (int64_t)min(max(y, 0), H - 1) * pitch + xc;
+                const uint32_t k = cls[off];
+                const float v = values[off];
+                const bool known = in && (k == 1u || k == 2u);
+                const double rw = tab->rho[m * 32 + c];
+                const double a = (k == 1u) ? 1.0 : projw;
+                const double wv = known ? a * rw : 0.0;
+                const double sv = known ? (double)v : 0.0;
+                zr[i] = wv * sv;
+                zi[i] = wv;
+            }
+        }
+
+        // 2. DFT along the support rows m (per column), transpose, DFT along n.
+        double* pl = reinterpret_cast<double*>(smem);   // one 32 x 33 plane at a time
+        fft32_pair(zr, zi, h, tw);                      // register k': Y[k1 = 2k'+h][n = c]
+#pragma unroll
+        for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zr[k];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) zr[i] = pl[c * kPlane + i + 16 * h];   // row k1 = c, n = i + 16h
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zi[k];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) zi[i] = pl[c * kPlane + i + 16 * h];
+        fft32_pair(zr, zi, h, tw);                      // register j: Z[k1 = c][k2 = 2j + h]
+
+        // 3. split Z = DFT(w s) + i DFT(w) using Z(-k), into the iteration layout
+        //    k = (j + 16 h, c).
+        double Rr[16], Ri[16], Wr[16], Wi[16];
+        {
+            const int nc = (32 - c) & 31;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zr[j];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
+                Wr[j] = pl[k1 * kPlane + c];      // Z.re(k)
+                Wi[j] = pl[nk1 * kPlane + nc];    // Z.re(-k)
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zi[j];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
+                const double ar = Wr[j], br = Wi[j];                                 // Z.re(k), Z.re(-k)
+                const double ai = pl[k1 * kPlane + c], bim = pl[nk1 * kPlane + nc];  // Z.im(k), Z.im(-k)
+                Rr[j] = 0.5 * (ar + br);
+                Ri[j] = 0.5 * (ai - bim);
+                Wr[j] = 0.5 * (ai + bim);
+                Wi[j] = 0.5 * (br - ar);
+            }
+            __syncthreads();
+        }
+        double2* T = reinterpret_cast<double2*>(smem);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) T[(j + 16 * h) * 32 + c] = make_double2(Wr[j], Wi[j]);
+        const double W0 = readlane_f64(Wr[0], 0);
+        __syncthreads();
+
+        // 4. greedy iterations.
+        const double g = (W0 > 0.0) ? gamma / W0 : 0.0;
+        double lbe = -1.0;   // packed local maximum
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            lbe = max_f64(lbe, pack_energy(fma(Rr[j], Rr[j], Ri[j] * Ri[j]), (uint32_t)(31 - 16 * h - j)));
+        const uint8_t* Tb = smem;
+        for (int it = 0; it < K; ++it) {
+            const double M = wave_allmax_f64(lbe);
+            const uint32_t mlo = (uint32_t)__builtin_amdgcn_readfirstlane(
+                (int)(uint32_t)(uint64_t)__double_as_longlong(M));
+            const int b1 = 31 - (int)(mlo & 31u);
+            // lanes holding the maximum all own row b1; the first is the smallest column
+            const unsigned long long hit = __ballot(lbe == M);
+            const int owner = hit ? (int)__builtin_ctzll(hit) : (b1 >> 4) << 5;
+            const int b2 = owner & 31;
+            const int jb = b1 & 15;
+            const double vr = Rr[jb], vi = Ri[jb];   // jb is wave-uniform: indexed register move
+            const double dr = g * readlane_f64(vr, owner);
+            const double di = g * readlane_f64(vi, owner);
+            if (lane == 0)
+                list[it] = make_float4(__uint_as_float((uint32_t)(b1 * 32 + b2)), (float)dr, (float)di, 0.0f);
+            const uint32_t L = ((uint32_t)h << 13) | ((uint32_t)((c - b2) & 31) << 4);
+            lbe = -1.0;
+            // issue all 16 table reads before the arithmetic so that their LDS
+            // latency overlaps
+            double2 wt[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t S = (uint32_t)((j - b1) & 31) << 9;   // wave-uniform row part
+                wt[j] = *reinterpret_cast<const double2*>(Tb + (S ^ L));
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const double2 wv = wt[j];
+                double xr = fma(-dr, wv.x, Rr[j]);
+                xr = fma(di, wv.y, xr);
+                double xi = fma(-dr, wv.y, Ri[j]);
+                xi = fma(-di, wv.x, xi);
+                Rr[j] = xr;
+                Ri[j] = xi;
+                lbe = max_f64(lbe, pack_energy(fma(xr, xr, xi * xi), (uint32_t)(31 - 16 * h - j)));
+            }
+        }
+        __syncthreads();
+
+        // 5. synthesis on the 16 block pixels; four lane groups split the list.
+        const int p = lane & 15, q = lane >> 4;
+        const int pm = 14 + (p >> 2), pn = 14 + (p & 3);
+        double gr = 0.0;
+        for (int it = q; it < K; it += 4) {
+            const float4 e = list[it];
+            const uint32_t bf = __float_as_uint(e.x);
+            const int t = ((int)(bf >> 5) * pm + (int)(bf & 31) * pn) & 31;
+            const double cs = s_tw[2 * t], sn = -s_tw[2 * t + 1];   // exp(+2 pi i t / 32)
+            gr = fma((double)e.y, cs, gr);
+            gr = fma(-(double)e.z, sn, gr);
+        }
+        gr += __shfl_xor(gr, 16);
+        gr += __shfl_xor(gr, 32);
+        if (lane < 16) {
+            const int y = 4 * bi + (p >> 2), x = 4 * bj + (p & 3);
+            const int64_t off = (int64_t)y * pitch + x;
+            const int64_t ooff = (int64_t)y * out_pitch + x;
             const uint32_t k = cls[off];
-            const float v = values[off];
-            const bool known = in && (k == 1u || k == 2u);
-            const double rw = tab->rho[m * 32 + c];
-            const double a = (k == 1u) ? 1.0 : projw;
-            const double wv = known ? a * rw : 0.0;
-            const double sv = known ? (double)v : 0.0;
-            zr[i] = wv * sv;
-            zi[i] = wv;
+            float o = (float)gr;
+            if (k == 1u || (overwrite == RFSR_RFSR && k == 2u)) o = values[off];
+            out[ooff] = o;
+            if (out_u8) out_u8[ooff] = (uint8_t)rintf(fminf(fmaxf(o, 0.0f), 255.0f));
         }
-    }
-
-    // 2. DFT along the support rows m (per column), transpose, DFT along n.
-    double* pl = reinterpret_cast<double*>(smem);   // one 32 x 33 plane at a time
-    fft32_pair(zr, zi, h, tw);                      // register k': Y[k1 = 2k'+h][n = c]
-#pragma unroll
-    for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zr[k];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) zr[i] = pl[c * kPlane + i + 16 * h];   // row k1 = c, n = i + 16h
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zi[k];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) zi[i] = pl[c * kPlane + i + 16 * h];
-    fft32_pair(zr, zi, h, tw);                      // register j: Z[k1 = c][k2 = 2j + h]
-
-    // 3. split Z = DFT(w s) + i DFT(w) using Z(-k), into the iteration layout
-    //    k = (j + 16 h, c).
-    double Rr[16], Ri[16], Wr[16], Wi[16];
-    {
-        const int nc = (32 - c) & 31;
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zr[j];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
-            Wr[j] = pl[k1 * kPlane + c];      // Z.re(k)
-            Wi[j] = pl[nk1 * kPlane + nc];    // Z.re(-k)
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zi[j];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
-            const double ar = Wr[j], br = Wi[j];                                 // Z.re(k), Z.re(-k)
-            const double ai = pl[k1 * kPlane + c], bim = pl[nk1 * kPlane + nc];  // Z.im(k), Z.im(-k)
-            Rr[j] = 0.5 * (ar + br);
-            Ri[j] = 0.5 * (ai - bim);
-            Wr[j] = 0.5 * (ai + bim);
-            Wi[j] = 0.5 * (br - ar);
-        }
-        __syncthreads();
-    }
-    double2* T = reinterpret_cast<double2*>(smem);
-#pragma unroll
-    for (int j = 0; j < 16; ++j) T[(j + 16 * h) * 32 + c] = make_double2(Wr[j], Wi[j]);
-    const double W0 = readlane_f64(Wr[0], 0);
-    __syncthreads();
-
-    // 4. greedy iterations.
-    const double g = (W0 > 0.0) ? gamma / W0 : 0.0;
-    double lbe = -1.0;   // packed local maximum
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-        lbe = max_f64(lbe, pack_energy(fma(Rr[j], Rr[j], Ri[j] * Ri[j]), (uint32_t)(31 - 16 * h - j)));
-    const uint8_t* Tb = smem;
-    for (int it = 0; it < K; ++it) {
-        const double M = wave_allmax_f64(lbe);
-        const uint32_t mlo = (uint32_t)__builtin_amdgcn_readfirstlane(
-            (int)(uint32_t)(uint64_t)__double_as_longlong(M));
-        const int b1 = 31 - (int)(mlo & 31u);
-        // lanes holding the maximum all own row b1; the first is the smallest column
-        const unsigned long long hit = __ballot(lbe == M);
-        const int owner = hit ? (int)__builtin_ctzll(hit) : (b1 >> 4) << 5;
-        const int b2 = owner & 31;
-        const int jb = b1 & 15;
-        const double vr = Rr[jb], vi = Ri[jb];   // jb is wave-uniform: indexed register move
-        const double dr = g * readlane_f64(vr, owner);
-        const double di = g * readlane_f64(vi, owner);
-        if (lane == 0)
-            list[it] = make_float4(__uint_as_float((uint32_t)(b1 * 32 + b2)), (float)dr, (float)di, 0.0f);
-        const uint32_t L = ((uint32_t)h << 13) | ((uint32_t)((c - b2) & 31) << 4);
-        lbe = -1.0;
-        // issue all 16 table reads before the arithmetic so that their LDS
-        // latency overlaps
-        double2 wt[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const uint32_t S = (uint32_t)((j - b1) & 31) << 9;   // wave-uniform row part
-            wt[j] = *reinterpret_cast<const double2*>(Tb + (S ^ L));
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const double2 wv = wt[j];
-            double xr = fma(-dr, wv.x, Rr[j]);
-            xr = fma(di, wv.y, xr);
-            double xi = fma(-dr, wv.y, Ri[j]);
-            xi = fma(-di, wv.x, xi);
-            Rr[j] = xr;
-            Ri[j] = xi;
-            lbe = max_f64(lbe, pack_energy(fma(xr, xr, xi * xi), (uint32_t)(31 - 16 * h - j)));
-        }
-    }
-    __syncthreads();
-
-    // 5. synthesis on the 16 block pixels; four lane groups split the list.
-    const int p = lane & 15, q = lane >> 4;
-    const int pm = 14 + (p >> 2), pn = 14 + (p & 3);
-    double gr = 0.0;
-    for (int it = q; it < K; it += 4) {
-        const float4 e = list[it];
-        const uint32_t bf = __float_as_uint(e.x);
-        const int t = ((int)(bf >> 5) * pm + (int)(bf & 31) * pn) & 31;
-        const double cs = s_tw[2 * t], sn = -s_tw[2 * t + 1];   // exp(+2 pi i t / 32)
-        gr = fma((double)e.y, cs, gr);
-        gr = fma(-(double)e.z, sn, gr);
-    }
-    gr += __shfl_xor(gr, 16);
-    gr += __shfl_xor(gr, 32);
-    if (lane < 16) {
-        const int y = 4 * bi + (p >> 2), x = 4 * bj + (p & 3);
-        const int64_t off = (int64_t)y * pitch + x;
-        const int64_t ooff = (int64_t)y * out_pitch + x;
-        const uint32_t k = cls[off];
-        float o = (float)gr;
-        if (k == 1u || (overwrite == RFSR_RFSR && k == 2u)) o = values[off];
-        out[ooff] = o;
-        if (out_u8) out_u8[ooff] = (uint8_t)rintf(fminf(fmaxf(o, 0.0f), 255.0f));
     }
 }
 
@@ -375,13 +387,12 @@ hipError_t launch_fsr_tables(FsrTables* t, double rho, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_fsr(const float* values, const uint8_t* cls, int H, int W, int64_t pitch,
-                      const rfsr_fsr_params& p, const FsrTables* tables, float* out,
-                      uint8_t* out_u8, int64_t out_pitch, hipStream_t s) {
-    const int nblk = (H / kBlock) * (W / kBlock);
+hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
+                      const FsrTables* tables, hipStream_t s) {
+    if (total_blocks <= 0) return hipSuccess;
     const size_t shmem = sizeof(float4) * (size_t)p.iters;
-    hipLaunchKernelGGL(fsr_block_kernel, dim3(nblk), dim3(64), shmem, s, values, cls, H, W, pitch,
-                       tables, out, out_u8, out_pitch, p.iters, p.gamma, p.proj_weight, p.overwrite);
+    hipLaunchKernelGGL(fsr_block_kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
+                       p.gamma, p.proj_weight, p.overwrite);
     return hipGetLastError();
 }
 

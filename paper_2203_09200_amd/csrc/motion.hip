@@ -14,8 +14,7 @@ namespace rfsr {
 
 namespace {
 
-constexpr int kTile = 16;          // forward ME tile: 16 x 16 pixels, 256 threads
-constexpr int kPad = 16;           // border of the window planes
+constexpr int kTile = kMeTile;     // forward ME tile: 16 x 16 pixels, 256 threads
 
 __device__ __forceinline__ bool inside(int y, int x, int H, int W) {
     return (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
@@ -138,20 +137,22 @@ __device__ __forceinline__ uint32_t me_search(const uint8_t* __restrict__ rowbas
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void me_forward_kernel(
-    const uint8_t* __restrict__ cur, const uint8_t* __restrict__ mask,
-    const uint8_t* __restrict__ ref, int H, int W, int64_t pitch, int8_t* __restrict__ mv_a,
-    int8_t* __restrict__ mv_b, int64_t mv_pitch, uint16_t* __restrict__ cost, int64_t cost_pitch,
-    uint8_t* __restrict__ nmap, unsigned long long* __restrict__ counters) {
+__global__ __launch_bounds__(256) void me_forward_kernel(Jobs<RefJob> js, int total,
+                                                         unsigned long long* __restrict__ counters) {
     using G = MeGeom<R>;
     __shared__ __align__(16) uint8_t s_ref[4 * G::COPY];
 
+    const int g = xcd_remap(blockIdx.x, total);
+    const RefJob j = job_at(js, g, &RefJob::g_tile);
+    if (j.H == 0) return;   // empty job (stale batch table)
+    const int H = j.H, W = j.W;
+    const int64_t pitch = j.pitch;
     const int tiles_x = (W + kTile - 1) / kTile;
-    const int ntiles = tiles_x * ((H + kTile - 1) / kTile);
-    const int tile = xcd_remap(blockIdx.x, ntiles);
+    const int tile = g - j.g_tile;
     const int y0 = (tile / tiles_x) * kTile, x0 = (tile % tiles_x) * kTile;
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
+    const uint8_t* __restrict__ ref = j.ref;
 
     // Stage the four shifted copies of the clamped reference window.
     {
@@ -186,8 +187,8 @@ __global__ __launch_bounds__(256) void me_forward_kernel(
             const int x = px - 1 + i;
             if (inside(y, x, H, W)) {
                 const int64_t off = (int64_t)y * pitch + x;
-                if (mask[off]) {
-                    const uint32_t v = cur[off];
+                if (j.cur_mask[off]) {
+                    const uint32_t v = j.cur[off];
                     tv |= v << (8 * i);
                     zv |= (v == 0 ? 0xFFu : 0u) << (8 * i);
                     n += 1;
@@ -217,10 +218,11 @@ __global__ __launch_bounds__(256) void me_forward_kernel(
     if (valid) {
         const int raster = (int)(best & 0x3FFu);
         const int vyi = raster / G::NC, s = raster - vyi * G::NC;
-        mv_a[(int64_t)py * mv_pitch + px] = (int8_t)(vyi - R);
-        mv_b[(int64_t)py * mv_pitch + px] = (int8_t)(s - R);
-        if (cost) cost[(int64_t)py * cost_pitch + px] = (uint16_t)(best >> 16);
-        if (nmap) nmap[(int64_t)py * W + px] = (uint8_t)n;
+        const int64_t o = (int64_t)py * j.opitch + px;
+        j.mv_a[o] = (int8_t)(vyi - R);
+        j.mv_b[o] = (int8_t)(s - R);
+        j.cost[(int64_t)py * j.cpitch + px] = (uint16_t)(best >> 16);
+        if (j.nmap_w) j.nmap_w[(int64_t)py * W + px] = (uint8_t)n;
     }
     if (counters) {
         unsigned long long cnt = 0;
@@ -239,10 +241,13 @@ __global__ __launch_bounds__(256) void me_forward_kernel(
 // (rows -kPad..H+kPad-1, columns -kPad..W+kPad-1) holds, for the template row
 // starting at column x-1: .x = the measured bytes of f_t (0 unmeasured or
 // outside), .y = 0xFF per byte where a measurement exists.
-__global__ void windows_kernel(const uint8_t* __restrict__ cur, const uint8_t* __restrict__ mask,
-                               int H, int W, int64_t pitch, uint2* __restrict__ fm) {
+__global__ void windows_kernel(Jobs<FrameJob> js) {
+    const FrameJob j = job_at(js, (int)blockIdx.x, &FrameJob::g_win);
+    if (j.H == 0) return;   // empty job (stale batch table)
+    if (!j.fm) return;
+    const int H = j.H, W = j.W;
     const int Wp = W + 2 * kPad, Hp = H + 2 * kPad;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = ((int)blockIdx.x - j.g_win) * 256 + (int)threadIdx.x;
     if (e >= Wp * Hp) return;
     const int y = e / Wp - kPad, x = e % Wp - kPad;
     uint32_t f = 0, m = 0;
@@ -251,72 +256,65 @@ __global__ void windows_kernel(const uint8_t* __restrict__ cur, const uint8_t* _
         for (int i = 0; i < 4; ++i) {
             const int xx = x - 1 + i;
             if ((unsigned)xx < (unsigned)W) {
-                const int64_t off = (int64_t)y * pitch + xx;
-                if (mask[off]) {
-                    f |= (uint32_t)cur[off] << (8 * i);
+                const int64_t off = (int64_t)y * j.pitch + xx;
+                if (j.cur_mask[off]) {
+                    f |= (uint32_t)j.cur[off] << (8 * i);
                     m |= 0xFFu << (8 * i);
                 }
             }
         }
     }
-    fm[e] = make_uint2(f, m);
+    j.fm[e] = make_uint2(f, m);
 }
 
-struct RevCtx {
-    const uint2* fm;   // padded window plane, origin at (kPad, kPad)
-    int Wp;
-    const uint8_t* nmap;
-    int H, W;
-};
-
 // Reverse template cost: template r (4 rows of reference bytes at q) against
-// the measured pixels of the current frame around s: S and its n.
-__device__ __forceinline__ uint32_t rev_cost(const RevCtx& c, const uint32_t (&r)[4], int sy, int sx) {
-    const uint2* p = c.fm + (int64_t)(sy - 1 + kPad) * c.Wp + (sx + kPad);
+// the measured pixels of the current frame around s.
+__device__ __forceinline__ uint32_t rev_cost(const RefJob& j, const uint32_t (&r)[4], int sy, int sx) {
+    const int Wp = j.W + 2 * kPad;
+    const uint2* p = j.fm + (int64_t)(sy - 1 + kPad) * Wp + (sx + kPad);
     uint32_t S = 0;
 #pragma unroll
     for (int dy = 0; dy < 4; ++dy) {
-        const uint2 v = p[dy * c.Wp];
+        const uint2 v = p[dy * Wp];
         S = __builtin_amdgcn_sad_u8(v.x, r[dy] & v.y, S);
     }
     return S;
 }
 
-__device__ __forceinline__ void ref_template(const uint8_t* __restrict__ ref, int H, int W,
-                                             int64_t pitch, int qy, int qx, uint32_t (&r)[4]) {
+__device__ __forceinline__ void ref_template(const RefJob& j, int qy, int qx, uint32_t (&r)[4]) {
 #pragma unroll
     for (int dy = 0; dy < 4; ++dy) {
-        const int64_t rowoff = (int64_t)clampi(qy - 1 + dy, 0, H - 1) * pitch;
+        const int64_t rowoff = (int64_t)clampi(qy - 1 + dy, 0, j.H - 1) * j.pitch;
         uint32_t v = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v |= (uint32_t)ref[rowoff + clampi(qx - 1 + i, 0, W - 1)] << (8 * i);
+        for (int i = 0; i < 4; ++i) v |= (uint32_t)j.ref[rowoff + clampi(qx - 1 + i, 0, j.W - 1)] << (8 * i);
         r[dy] = v;
     }
 }
 
 // Reverse motion field for RME: for every q the minimiser of
 // (S_rev/n_rev, |u|_1, raster(u)) over u in [-R,R]^2 with q+u in the frame.
-__global__ __launch_bounds__(256) void reverse_me_kernel(
-    RevCtx c, const uint8_t* __restrict__ ref, int64_t pitch, int R, int8_t* __restrict__ ra,
-    int8_t* __restrict__ rb, unsigned long long* __restrict__ counters) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = e < c.H * c.W;
+__global__ __launch_bounds__(256) void reverse_me_kernel(Jobs<RefJob> js, int R,
+                                                         unsigned long long* __restrict__ counters) {
+    const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_px);
+    if (j.H == 0) return;   // empty job (stale batch table)
+    const int e = ((int)blockIdx.x - j.g_px) * 256 + (int)threadIdx.x;
     unsigned long long evals = 0;
-    if (valid) {
-        const int qy = e / c.W, qx = e - qy * c.W;
+    if (e < j.H * j.W) {
+        const int qy = e / j.W, qx = e - qy * j.W;
         uint32_t r[4];
-        ref_template(ref, c.H, c.W, pitch, qy, qx, r);
+        ref_template(j, qy, qx, r);
         uint32_t bS = 0, bn = 1, bl1 = 0;
         int bu = 0, bv = 0;
         bool has = false;
         for (int uy = -R; uy <= R; ++uy) {
             const int sy = qy + uy;
-            if ((unsigned)sy >= (unsigned)c.H) continue;
+            if ((unsigned)sy >= (unsigned)j.H) continue;
             for (int ux = -R; ux <= R; ++ux) {
                 const int sx = qx + ux;
-                if ((unsigned)sx >= (unsigned)c.W) continue;
-                const uint32_t S = rev_cost(c, r, sy, sx);
-                const uint32_t n = c.nmap[(int64_t)sy * c.W + sx];
+                if ((unsigned)sx >= (unsigned)j.W) continue;
+                const uint32_t S = rev_cost(j, r, sy, sx);
+                const uint32_t n = j.nmap[(int64_t)sy * j.W + sx];
                 const uint32_t l1 = (uint32_t)(abs(uy) + abs(ux));
                 const uint32_t lhs = S * bn, rhs = bS * n;
                 ++evals;
@@ -325,8 +323,8 @@ __global__ __launch_bounds__(256) void reverse_me_kernel(
                 }
             }
         }
-        ra[e] = (int8_t)bu;
-        rb[e] = (int8_t)bv;
+        j.ra[e] = (int8_t)bu;
+        j.rb[e] = (int8_t)bv;
     }
     if (counters) {
         evals = wave_sum_u64(evals);
@@ -334,27 +332,18 @@ __global__ __launch_bounds__(256) void reverse_me_kernel(
     }
 }
 
-struct AcceptIO {
-    const int8_t* mv_a;
-    const int8_t* mv_b;
-    int64_t mv_pitch;
-    uint8_t* accept;
-    int64_t acc_pitch;
-    const uint8_t* cur_mask;   // with ref_mask: restrict to projectable pixels
-    const uint8_t* ref_mask;
-    int64_t pitch;
-};
-
-__global__ void rme_accept_kernel(AcceptIO io, int H, int W, const int8_t* __restrict__ ra,
-                                  const int8_t* __restrict__ rb, unsigned long long* counters) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void rme_accept_kernel(Jobs<RefJob> js, unsigned long long* counters) {
+    const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_px);
+    if (j.H == 0) return;   // empty job (stale batch table)
+    const int e = ((int)blockIdx.x - j.g_px) * 256 + (int)threadIdx.x;
     unsigned long long acc_cnt = 0;
-    if (e < H * W) {
-        const int y = e / W, x = e - y * W;
-        const int a = io.mv_a[(int64_t)y * io.mv_pitch + x], b = io.mv_b[(int64_t)y * io.mv_pitch + x];
-        const int q = (y + a) * W + (x + b);
-        const bool ok = ra[q] == -a && rb[q] == -b;
-        io.accept[(int64_t)y * io.acc_pitch + x] = ok;
+    if (e < j.H * j.W) {
+        const int y = e / j.W, x = e - y * j.W;
+        const int64_t o = (int64_t)y * j.opitch + x;
+        const int a = j.mv_a[o], b = j.mv_b[o];
+        const int q = (y + a) * j.W + (x + b);
+        const bool ok = j.ra[q] == -a && j.rb[q] == -b;
+        j.accept[o] = ok;
         acc_cnt = ok;
     }
     if (counters) {
@@ -363,30 +352,37 @@ __global__ void rme_accept_kernel(AcceptIO io, int H, int W, const int8_t* __res
     }
 }
 
+// Is p a pixel whose decision matters (projectable: missing now, measured at
+// p+v)?  Always true without a reference mask.
+__device__ __forceinline__ bool projectable(const RefJob& j, int y, int x, int a, int b) {
+    if (!j.ref_mask) return true;
+    return j.cur_mask[(int64_t)y * j.pitch + x] == 0 && j.ref_mask[(int64_t)(y + a) * j.pitch + (x + b)] != 0;
+}
+
 // RMC (DENSE, offsets [-rr, rr]^2) and FRMC ({-7,-3,-1,0,1,3,7}^2) at pixel p
 // with vector (a, b): accept iff S(p,v)/n(p) < S(p+d, v-d)/n(p+d) for every
 // red d with p+d in the frame.  Reds are tried in raster order and the test
 // stops at the first loser.  evals counts the red costs evaluated.
 template <bool DENSE>
-__device__ __forceinline__ bool reverse_test(const RevCtx& c, const uint8_t* __restrict__ ref,
-                                             int64_t pitch, int py, int px, int a, int b,
-                                             uint32_t Sg, uint32_t ng, int rr,
+__device__ __forceinline__ bool reverse_test(const RefJob& j, int py, int px, int a, int b, int rr,
                                              unsigned long long& evals) {
     uint32_t r[4];
-    ref_template(ref, c.H, c.W, pitch, py + a, px + b, r);
+    ref_template(j, py + a, px + b, r);
+    const uint32_t Sg = j.cost[(int64_t)py * j.cpitch + px];
+    const uint32_t ng = j.nmap[(int64_t)py * j.W + px];
     bool ok = true;
     // FRMC offsets {-7,-3,-1,0,1,3,7}: sign(i-3) * (2^|i-3| - 1)
     const int n1 = DENSE ? 2 * rr + 1 : 7;
     for (int iy = 0; iy < n1 && ok; ++iy) {
         const int dy = DENSE ? iy - rr : (iy < 3 ? -1 : 1) * ((1 << abs(iy - 3)) - 1);
         const int sy = py + dy;
-        if ((unsigned)sy >= (unsigned)c.H) continue;
+        if ((unsigned)sy >= (unsigned)j.H) continue;
         for (int ix = 0; ix < n1; ++ix) {
             const int dx = DENSE ? ix - rr : (ix < 3 ? -1 : 1) * ((1 << abs(ix - 3)) - 1);
             const int sx = px + dx;
-            if ((dy | dx) == 0 || (unsigned)sx >= (unsigned)c.W) continue;
-            const uint32_t S = rev_cost(c, r, sy, sx);
-            const uint32_t n = c.nmap[(int64_t)sy * c.W + sx];
+            if ((dy | dx) == 0 || (unsigned)sx >= (unsigned)j.W) continue;
+            const uint32_t S = rev_cost(j, r, sy, sx);
+            const uint32_t n = j.nmap[(int64_t)sy * j.W + sx];
             ++evals;
             if (S * ng <= Sg * n) { ok = false; break; }
         }
@@ -394,30 +390,25 @@ __device__ __forceinline__ bool reverse_test(const RevCtx& c, const uint8_t* __r
     return ok;
 }
 
-// RMC / FRMC over every pixel (stand-alone checks).  With io.ref_mask set,
-// only projectable pixels (missing now, measured at p+v) are tested; the
-// decision elsewhere is 0.
+// RMC / FRMC over every pixel (stand-alone checks); with a reference mask
+// only projectable pixels are tested and the decision elsewhere is 0.
 template <bool DENSE>
-__global__ __launch_bounds__(256) void rmc_kernel(
-    RevCtx c, AcceptIO io, const uint8_t* __restrict__ ref, const uint16_t* __restrict__ cost,
-    int64_t cost_pitch, int rr, unsigned long long* __restrict__ counters) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void rmc_kernel(Jobs<RefJob> js, int rr,
+                                                  unsigned long long* __restrict__ counters) {
+    const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_px);
+    if (j.H == 0) return;   // empty job (stale batch table)
+    const int e = ((int)blockIdx.x - j.g_px) * 256 + (int)threadIdx.x;
     unsigned long long evals = 0, checked = 0, accepted = 0;
-    if (e < c.H * c.W) {
-        const int py = e / c.W, px = e - py * c.W;
-        const int a = io.mv_a[(int64_t)py * io.mv_pitch + px];
-        const int b = io.mv_b[(int64_t)py * io.mv_pitch + px];
-        bool ok = true;
-        if (io.ref_mask) {
-            ok = io.cur_mask[(int64_t)py * io.pitch + px] == 0 &&
-                 io.ref_mask[(int64_t)(py + a) * io.pitch + (px + b)] != 0;
-        }
+    if (e < j.H * j.W) {
+        const int py = e / j.W, px = e - py * j.W;
+        const int64_t o = (int64_t)py * j.opitch + px;
+        const int a = j.mv_a[o], b = j.mv_b[o];
+        bool ok = projectable(j, py, px, a, b);
         if (ok) {
             checked = 1;
-            ok = reverse_test<DENSE>(c, ref, io.pitch, py, px, a, b, cost[(int64_t)py * cost_pitch + px],
-                                     c.nmap[(int64_t)py * c.W + px], rr, evals);
+            ok = reverse_test<DENSE>(j, py, px, a, b, rr, evals);
         }
-        io.accept[(int64_t)py * io.acc_pitch + px] = ok;
+        j.accept[o] = ok;
         accepted = ok;
     }
     if (counters) {
@@ -432,37 +423,32 @@ __global__ __launch_bounds__(256) void rmc_kernel(
     }
 }
 
-// FRMC after NNC (the cascade).  A workgroup owns a run of kFrmcTile raster
-// pixels: it collects the pixels that need the test (NNC accepted and, in
-// the frame path, projectable) into an LDS list, then runs FRMC over that
+// FRMC after NNC (the cascade).  A workgroup owns a run of kFrmcRun raster
+// pixels: it collects the pixels that need the test (NNC accepted and, with a
+// reference mask, projectable) into an LDS list, then runs FRMC over that
 // list with all its threads, so that waves stay full although most pixels
 // need no test.  Every pixel of the run gets its decision written.
-constexpr int kFrmcTile = 2048;
-
-__global__ __launch_bounds__(256) void frmc_tile_kernel(
-    RevCtx c, AcceptIO io, const uint8_t* __restrict__ ref, const uint16_t* __restrict__ cost,
-    int64_t cost_pitch, unsigned long long* __restrict__ counters) {
-    __shared__ int s_list[kFrmcTile];
+__global__ __launch_bounds__(256) void frmc_tile_kernel(Jobs<RefJob> js,
+                                                        unsigned long long* __restrict__ counters) {
+    __shared__ int s_list[kFrmcRun];
     __shared__ unsigned s_n;
+    const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_frmc);
+    if (j.H == 0) return;   // empty job (stale batch table)
     const int tid = threadIdx.x;
-    const int npx = c.H * c.W;
-    const int e0 = blockIdx.x * kFrmcTile;
+    const int npx = j.H * j.W;
+    const int e0 = ((int)blockIdx.x - j.g_frmc) * kFrmcRun;
     if (tid == 0) s_n = 0u;
     __syncthreads();
     unsigned long long checked = 0;
-    for (int k = 0; k < kFrmcTile / 256; ++k) {
+    for (int k = 0; k < kFrmcRun / 256; ++k) {
         const int e = e0 + k * 256 + tid;
         bool need = false;
         if (e < npx) {
-            const int y = e / c.W, x = e - y * c.W;
-            need = io.accept[(int64_t)y * io.acc_pitch + x] != 0;   // NNC decision
-            if (need && io.ref_mask) {
-                const int va = io.mv_a[(int64_t)y * io.mv_pitch + x];
-                const int vb = io.mv_b[(int64_t)y * io.mv_pitch + x];
-                need = io.cur_mask[(int64_t)y * io.pitch + x] == 0 &&
-                       io.ref_mask[(int64_t)(y + va) * io.pitch + (x + vb)] != 0;
-            }
-            if (!need) io.accept[(int64_t)y * io.acc_pitch + x] = 0;
+            const int y = e / j.W, x = e - y * j.W;
+            const int64_t o = (int64_t)y * j.opitch + x;
+            need = j.accept[o] != 0;   // NNC decision
+            if (need) need = projectable(j, y, x, j.mv_a[o], j.mv_b[o]);
+            if (!need) j.accept[o] = 0;
         }
         // wave-aggregated append to the LDS list
         const unsigned long long m = __ballot(need);
@@ -478,13 +464,10 @@ __global__ __launch_bounds__(256) void frmc_tile_kernel(
     unsigned long long evals = 0, accepted = 0;
     for (unsigned i = tid; i < n; i += 256) {
         const int e = s_list[i];
-        const int py = e / c.W, px = e - py * c.W;
-        const int a = io.mv_a[(int64_t)py * io.mv_pitch + px];
-        const int b = io.mv_b[(int64_t)py * io.mv_pitch + px];
-        const bool ok = reverse_test<false>(c, ref, io.pitch, py, px, a, b,
-                                            cost[(int64_t)py * cost_pitch + px],
-                                            c.nmap[(int64_t)py * c.W + px], 0, evals);
-        io.accept[(int64_t)py * io.acc_pitch + px] = ok;
+        const int py = e / j.W, px = e - py * j.W;
+        const int64_t o = (int64_t)py * j.opitch + px;
+        const bool ok = reverse_test<false>(j, py, px, j.mv_a[o], j.mv_b[o], 0, evals);
+        j.accept[o] = ok;
         accepted += ok;
     }
     if (counters) {
@@ -521,42 +504,46 @@ __device__ __forceinline__ int median9(int (&v)[9]) {
     return med3(lo, md, hi);
 }
 
-__global__ void median_kernel(const int8_t* __restrict__ a, const int8_t* __restrict__ b,
-                              int64_t mv_pitch, int H, int W, int8_t* __restrict__ ma,
-                              int8_t* __restrict__ mb) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void median_kernel(Jobs<RefJob> js) {
+    const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_px);
+    if (j.H == 0) return;   // empty job (stale batch table)
+    const int e = ((int)blockIdx.x - j.g_px) * 256 + (int)threadIdx.x;
+    const int H = j.H, W = j.W;
     if (e >= H * W) return;
     const int y = e / W, x = e - y * W;
     int va[9], vb[9];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) {
-        const int64_t ro = (int64_t)clampi(y - 1 + dy, 0, H - 1) * mv_pitch;
+        const int64_t ro = (int64_t)clampi(y - 1 + dy, 0, H - 1) * j.opitch;
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
             const int xx = clampi(x - 1 + dx, 0, W - 1);
-            va[3 * dy + dx] = a[ro + xx];
-            vb[3 * dy + dx] = b[ro + xx];
+            va[3 * dy + dx] = j.mv_a[ro + xx];
+            vb[3 * dy + dx] = j.mv_b[ro + xx];
         }
     }
-    ma[e] = (int8_t)median9(va);
-    mb[e] = (int8_t)median9(vb);
+    j.ma[e] = (int8_t)median9(va);
+    j.mb[e] = (int8_t)median9(vb);
 }
 
 // NNC decision (the cascade's FRMC reads it back from `accept`).
-__global__ void nnc_kernel(const int8_t* __restrict__ ma, const int8_t* __restrict__ mb, int H,
-                           int W, uint8_t* __restrict__ accept, int64_t acc_pitch,
-                           unsigned long long* counters, bool count) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void nnc_kernel(Jobs<RefJob> js, unsigned long long* counters, bool count) {
+    const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_px);
+    if (j.H == 0) return;   // empty job (stale batch table)
+    const int e = ((int)blockIdx.x - j.g_px) * 256 + (int)threadIdx.x;
+    const int H = j.H, W = j.W;
     unsigned long long acc_cnt = 0;
     if (e < H * W) {
         const int y = e / W, x = e - y * W;
+        const int8_t* __restrict__ ma = j.ma;
+        const int8_t* __restrict__ mb = j.mb;
         const int a = ma[e], b = mb[e];
         bool ok = true;
         if (y > 0) ok &= abs(a - ma[e - W]) + abs(b - mb[e - W]) <= 1;
         if (y < H - 1) ok &= abs(a - ma[e + W]) + abs(b - mb[e + W]) <= 1;
         if (x > 0) ok &= abs(a - ma[e - 1]) + abs(b - mb[e - 1]) <= 1;
         if (x < W - 1) ok &= abs(a - ma[e + 1]) + abs(b - mb[e + 1]) <= 1;
-        accept[(int64_t)y * acc_pitch + x] = ok;
+        j.accept[(int64_t)y * j.opitch + x] = ok;
         acc_cnt = ok;
     }
     if (count && counters) {
@@ -565,63 +552,61 @@ __global__ void nnc_kernel(const int8_t* __restrict__ ma, const int8_t* __restri
     }
 }
 
-__global__ void accept_all_kernel(uint8_t* __restrict__ accept, int64_t acc_pitch, int H, int W,
-                                  unsigned long long* counters) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < H * W) accept[(int64_t)(e / W) * acc_pitch + (e % W)] = 1;
-    if (counters && blockIdx.x == 0 && threadIdx.x == 0)
-        atomicAdd(counters + RFSR_CNT_ACCEPTED, (unsigned long long)H * W);
+__global__ void accept_all_kernel(Jobs<RefJob> js, unsigned long long* counters) {
+    const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_px);
+    if (j.H == 0) return;   // empty job (stale batch table)
+    const int e = ((int)blockIdx.x - j.g_px) * 256 + (int)threadIdx.x;
+    unsigned long long acc_cnt = 0;
+    if (e < j.H * j.W) {
+        j.accept[(int64_t)(e / j.W) * j.opitch + (e % j.W)] = 1;
+        acc_cnt = 1;
+    }
+    if (counters) {
+        acc_cnt = wave_sum_u64(acc_cnt);
+        if ((threadIdx.x & 63) == 0) atomicAdd(counters + RFSR_CNT_ACCEPTED, acc_cnt);
+    }
 }
 
 // ----------------------------------------------------------- projection ----
-struct ProjArgs {
-    ProjRef r[3];
-};
-
-__global__ void project_kernel(const uint8_t* __restrict__ cur, const uint8_t* __restrict__ cur_mask,
-                               int H, int W, int64_t pitch, int nref, ProjArgs pa, int64_t ipitch,
-                               float* __restrict__ values, uint8_t* __restrict__ cls) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= H * W) return;
+__global__ void project_kernel(Jobs<FrameJob> js) {
+    const FrameJob j = job_at(js, (int)blockIdx.x, &FrameJob::g_px);
+    if (j.H == 0) return;   // empty job (stale batch table)
+    const int e = ((int)blockIdx.x - j.g_px) * 256 + (int)threadIdx.x;
+    const int W = j.W;
+    if (e >= j.H * W) return;
     const int y = e / W, x = e - y * W;
-    const int64_t off = (int64_t)y * pitch + x;
-    if (cur_mask[off]) {
-        values[e] = (float)cur[off];
-        cls[e] = 1;
+    const int64_t off = (int64_t)y * j.pitch + x;
+    if (j.cur_mask[off]) {
+        j.values[e] = (float)j.cur[off];
+        j.cls[e] = 1;
         return;
     }
     uint32_t total = 0, count = 0;
-    for (int k = 0; k < nref; ++k) {
-        const ProjRef& r = pa.r[k];
-        const int64_t io = (int64_t)y * ipitch + x;
-        if (!r.accept[io]) continue;
-        const int qy = y + r.mv_a[io], qx = x + r.mv_b[io];
-        const int64_t qo = (int64_t)qy * pitch + qx;
-        if (r.mask[qo]) {
-            total += r.meas[qo];
+    const int64_t io = (int64_t)y * j.opitch + x;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {   // constant indices keep the job's arrays in registers
+        if (k >= j.nref || !j.accept[k][io]) continue;
+        const int qy = y + j.mv_a[k][io], qx = x + j.mv_b[k][io];
+        const int64_t qo = (int64_t)qy * j.pitch + qx;
+        if (j.ref_mask[k][qo]) {
+            total += j.ref_meas[k][qo];
             count += 1;
         }
     }
-    values[e] = count ? (float)total / (float)count : 0.0f;
-    cls[e] = count ? 2 : 0;
+    j.values[e] = count ? (float)total / (float)count : 0.0f;
+    j.cls[e] = count ? 2 : 0;
 }
 
 // ------------------------------------------------------------- dispatch ----
 template <int R>
-hipError_t launch_me_r(const uint8_t* cur, const uint8_t* mask, const uint8_t* ref, int H, int W,
-                       int64_t pitch, int8_t* a, int8_t* b, int64_t mvp, uint16_t* cost,
-                       int64_t cp, uint8_t* nmap, unsigned long long* counters, hipStream_t s) {
-    const int nt = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
-    hipLaunchKernelGGL(me_forward_kernel<R>, dim3(nt), dim3(256), 0, s, cur, mask, ref, H, W, pitch,
-                       a, b, mvp, cost, cp, nmap, counters);
+hipError_t launch_me_r(const Jobs<RefJob>& js, int total, unsigned long long* counters, hipStream_t s) {
+    hipLaunchKernelGGL(me_forward_kernel<R>, dim3(total), dim3(256), 0, s, js, total, counters);
     return hipGetLastError();
 }
 
-hipError_t launch_me(int R, const uint8_t* cur, const uint8_t* mask, const uint8_t* ref, int H,
-                     int W, int64_t pitch, int8_t* a, int8_t* b, int64_t mvp, uint16_t* cost,
-                     int64_t cp, uint8_t* nmap, unsigned long long* counters, hipStream_t s) {
+hipError_t launch_me(int R, const Jobs<RefJob>& js, int total, unsigned long long* counters, hipStream_t s) {
 #define RFSR_ME_CASE(r) \
-    case r: return launch_me_r<r>(cur, mask, ref, H, W, pitch, a, b, mvp, cost, cp, nmap, counters, s);
+    case r: return launch_me_r<r>(js, total, counters, s);
     switch (R) {
         RFSR_ME_CASE(0) RFSR_ME_CASE(1) RFSR_ME_CASE(2) RFSR_ME_CASE(3) RFSR_ME_CASE(4)
         RFSR_ME_CASE(5) RFSR_ME_CASE(6) RFSR_ME_CASE(7) RFSR_ME_CASE(8) RFSR_ME_CASE(9)
@@ -632,114 +617,62 @@ hipError_t launch_me(int R, const uint8_t* cur, const uint8_t* mask, const uint8
 #undef RFSR_ME_CASE
 }
 
-inline unsigned grid1(int n, int b = 256) { return (unsigned)((n + b - 1) / b); }
-
 }  // namespace
 
-// Workspace of run_motion_check: nmap, window plane, reverse field, medians,
-// green cost (when the caller passes none).
-struct MotionLayout {
-    size_t nmap, fm, ra, rb, ma, mb, cost, total;
-    MotionLayout(int H, int W) {
-        const size_t px = (size_t)H * W;
-        size_t o = 0;
-        nmap = o; o = align256(o + px);
-        fm = o; o = align256(o + sizeof(uint2) * (size_t)(H + 2 * kPad) * (W + 2 * kPad));
-        ra = o; o = align256(o + px);
-        rb = o; o = align256(o + px);
-        ma = o; o = align256(o + px);
-        mb = o; o = align256(o + px);
-        cost = o; o = align256(o + 2 * px);
-        total = o;
-    }
-};
+bool check_needs_windows(int check) {
+    return check == RFSR_CHECK_RME || check == RFSR_CHECK_RMC || check == RFSR_CHECK_FRMC ||
+           check == RFSR_CHECK_NNC_FRMC;
+}
 
-size_t motion_ws_bytes(int H, int W, const rfsr_me_params&) { return MotionLayout(H, W).total; }
+hipError_t launch_windows(const Jobs<FrameJob>& js, int total_groups, hipStream_t s) {
+    if (total_groups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(windows_kernel, dim3(total_groups), dim3(256), 0, s, js);
+    return hipGetLastError();
+}
 
-hipError_t run_motion_check(const uint8_t* cur, const uint8_t* cur_mask, const uint8_t* ref, int H,
-                            int W, int64_t pitch, const rfsr_me_params& me, int8_t* mv_a,
-                            int8_t* mv_b, int64_t mv_pitch, uint8_t* accept, int64_t acc_pitch,
-                            uint16_t* cost, int64_t cost_pitch, unsigned long long* counters,
-                            void* ws, bool windows_ready, const uint8_t* ref_mask_for_need,
-                            hipStream_t s) {
-    const MotionLayout L(H, W);
-    uint8_t* base = static_cast<uint8_t*>(ws);
-    uint8_t* nmap = base + L.nmap;
-    uint2* fm = reinterpret_cast<uint2*>(base + L.fm);
-    if (!cost) {
-        cost = reinterpret_cast<uint16_t*>(base + L.cost);
-        cost_pitch = W;
-    }
-    hipError_t err = launch_me(me.search, cur, cur_mask, ref, H, W, pitch, mv_a, mv_b, mv_pitch, cost,
-                               cost_pitch, nmap, counters, s);
+hipError_t launch_project(const Jobs<FrameJob>& js, int total_groups, hipStream_t s) {
+    if (total_groups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(project_kernel, dim3(total_groups), dim3(256), 0, s, js);
+    return hipGetLastError();
+}
+
+hipError_t launch_motion(const Jobs<RefJob>& js, int total_tiles, int total_px, int total_frmc,
+                         const rfsr_me_params& me, unsigned long long* counters, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    hipError_t err = launch_me(me.search, js, total_tiles, counters, s);
     if (err != hipSuccess) return err;
-
-    const int npx = H * W;
-    const int check = me.check;
-    const bool need_windows = check == RFSR_CHECK_RME || check == RFSR_CHECK_RMC ||
-                              check == RFSR_CHECK_FRMC || check == RFSR_CHECK_NNC_FRMC;
-    if (need_windows && !windows_ready) {
-        const int nfm = (H + 2 * kPad) * (W + 2 * kPad);
-        hipLaunchKernelGGL(windows_kernel, dim3(grid1(nfm)), dim3(256), 0, s, cur, cur_mask, H, W, pitch, fm);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-    }
-    RevCtx rc{fm, W + 2 * kPad, nmap, H, W};
-    AcceptIO io{mv_a, mv_b, mv_pitch, accept, acc_pitch,
-                ref_mask_for_need ? cur_mask : nullptr, ref_mask_for_need, pitch};
     const int rr = me.rmc_radius > 0 ? me.rmc_radius : me.search;
-    switch (check) {
+    const dim3 gpx(total_px), blk(256);
+    switch (me.check) {
         case RFSR_CHECK_NONE:
-            hipLaunchKernelGGL(accept_all_kernel, dim3(grid1(npx)), dim3(256), 0, s, accept, acc_pitch, H, W,
-                               counters);
+            hipLaunchKernelGGL(accept_all_kernel, gpx, blk, 0, s, js, counters);
             break;
-        case RFSR_CHECK_RME: {
-            int8_t* ra = reinterpret_cast<int8_t*>(base + L.ra);
-            int8_t* rb = reinterpret_cast<int8_t*>(base + L.rb);
-            hipLaunchKernelGGL(reverse_me_kernel, dim3(grid1(npx)), dim3(256), 0, s, rc, ref, pitch,
-                               me.search, ra, rb, counters);
+        case RFSR_CHECK_RME:
+            hipLaunchKernelGGL(reverse_me_kernel, gpx, blk, 0, s, js, me.search, counters);
             if ((err = hipGetLastError()) != hipSuccess) return err;
-            hipLaunchKernelGGL(rme_accept_kernel, dim3(grid1(npx)), dim3(256), 0, s, io, H, W, ra, rb,
-                               counters);
+            hipLaunchKernelGGL(rme_accept_kernel, gpx, blk, 0, s, js, counters);
             break;
-        }
         case RFSR_CHECK_RMC:
-            hipLaunchKernelGGL((rmc_kernel<true>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref, cost,
-                               cost_pitch, rr, counters);
+            hipLaunchKernelGGL((rmc_kernel<true>), gpx, blk, 0, s, js, rr, counters);
             break;
         case RFSR_CHECK_FRMC:
-            hipLaunchKernelGGL((rmc_kernel<false>), dim3(grid1(npx)), dim3(256), 0, s, rc, io, ref, cost,
-                               cost_pitch, rr, counters);
+            hipLaunchKernelGGL((rmc_kernel<false>), gpx, blk, 0, s, js, rr, counters);
             break;
         case RFSR_CHECK_NNC:
         case RFSR_CHECK_NNC_FRMC: {
-            const bool cascade = check == RFSR_CHECK_NNC_FRMC;
-            int8_t* ma = reinterpret_cast<int8_t*>(base + L.ma);
-            int8_t* mb = reinterpret_cast<int8_t*>(base + L.mb);
-            hipLaunchKernelGGL(median_kernel, dim3(grid1(npx)), dim3(256), 0, s, mv_a, mv_b, mv_pitch, H, W,
-                               ma, mb);
+            const bool cascade = me.check == RFSR_CHECK_NNC_FRMC;
+            hipLaunchKernelGGL(median_kernel, gpx, blk, 0, s, js);
             if ((err = hipGetLastError()) != hipSuccess) return err;
-            hipLaunchKernelGGL(nnc_kernel, dim3(grid1(npx)), dim3(256), 0, s, ma, mb, H, W, accept, acc_pitch,
-                               counters, !cascade);
+            hipLaunchKernelGGL(nnc_kernel, gpx, blk, 0, s, js, counters, !cascade);
             if (cascade) {
                 if ((err = hipGetLastError()) != hipSuccess) return err;
-                hipLaunchKernelGGL(frmc_tile_kernel, dim3(grid1(npx, kFrmcTile)), dim3(256), 0, s, rc, io, ref,
-                                   cost, cost_pitch, counters);
+                hipLaunchKernelGGL(frmc_tile_kernel, dim3(total_frmc), blk, 0, s, js, counters);
             }
             break;
         }
         default:
             return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_project(const uint8_t* cur, const uint8_t* cur_mask, int H, int W, int64_t pitch,
-                          int nref, const ProjRef* refs, int64_t ipitch, float* values, uint8_t* cls,
-                          hipStream_t s) {
-    ProjArgs pa{};
-    for (int k = 0; k < nref && k < 3; ++k) pa.r[k] = refs[k];
-    hipLaunchKernelGGL(project_kernel, dim3(grid1(H * W)), dim3(256), 0, s, cur, cur_mask, H, W, pitch,
-                       nref, pa, ipitch, values, cls);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol(R):
     lib = R.lib()
     for n in declared_functions():
         assert hasattr(lib, n), n
-    assert lib.rfsr_version() == 10000
+    assert lib.rfsr_version() == 10100
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.rfsr_status_string(code).startswith(b"RFSR_")
 
@@ -122,3 +122,98 @@ def test_binding_refuses_host_tensors(R):
         R.motion_check(x, x, x)
     with pytest.raises(R.RfsrError):
         R.fsr_blocks(torch.zeros((8, 8)), x)
+
+
+def _descs(R, shapes, nrefs, base=1 << 20):
+    """Descriptors with fake (never dereferenced) device addresses."""
+    ds = (R.FrameDesc * len(shapes))()
+    a = base
+    for d, (H, W), nref in zip(ds, shapes, nrefs):
+        d.cur, d.cur_mask, d.out = a, a + 0x1000, a + 0x2000
+        for k in range(nref):
+            d.ref_recon[k], d.ref_meas[k], d.ref_mask[k] = a + 0x3000 + k, a + 0x4000 + k, a + 0x5000 + k
+        d.nref, d.H, d.W, d.pitch = nref, H, W, W
+        a += 1 << 24
+    return ds
+
+
+def test_batch_sizes_and_validation(R):
+    lib = R.lib()
+    me, fsr = R.MEParams().c(), R.FSRParams().c()
+    shapes, nrefs = [(64, 64), (96, 128), (1080, 1920)], [3, 0, 2]
+    ds = _descs(R, shapes, nrefs)
+    ws = lib.rfsr_batch_workspace_bytes(ds, 3, ctypes.byref(me), ctypes.byref(fsr))
+    singles = sum(R.workspace_bytes(H, W, max(n, 1)) for (H, W), n in zip(shapes, nrefs))
+    # per-frame scratch plus one set of FSR tables; a frame without references
+    # needs no reference planes
+    assert 0 < ws <= singles
+    tb = lib.rfsr_batch_table_bytes(ds, 3)
+    assert tb % 256 == 0 and tb > 256
+    # invalid descriptors: bad shape, nref, null planes, n out of range
+    for mut in (lambda d: setattr(d, "H", 6), lambda d: setattr(d, "nref", 4),
+                lambda d: setattr(d, "cur", None), lambda d: setattr(d, "pitch", 8)):
+        bad = _descs(R, shapes, nrefs)
+        mut(bad[2])
+        assert lib.rfsr_batch_workspace_bytes(bad, 3, ctypes.byref(me), ctypes.byref(fsr)) == 0
+        assert lib.rfsr_batch_table_bytes(bad, 3) == 0
+    assert lib.rfsr_batch_table_bytes(ds, 0) == 0
+    assert lib.rfsr_batch_table_bytes(None, 1) == 0
+    bad = _descs(R, shapes, nrefs)
+    bad[0].ref_meas[2] = None
+    assert lib.rfsr_batch_table_bytes(bad, 3) == 0
+
+
+def test_batch_tables_are_keyed_to_their_descriptors(R):
+    """The job-table image is built on the host: its header counts the jobs and
+    carries a key that changes with any descriptor, the check or the
+    workspace address."""
+    import struct
+    lib = R.lib()
+    me = R.MEParams().c()
+    shapes, nrefs = [(64, 64), (96, 128)], [3, 1]
+    ds = _descs(R, shapes, nrefs)
+    tb = lib.rfsr_batch_table_bytes(ds, 2)
+    img = ctypes.create_string_buffer(tb)
+
+    def key(descs, mc, ws):
+        assert lib.rfsr_batch_write_tables(descs, 2, ctypes.byref(mc), ctypes.c_void_p(ws), img, tb) == 0
+        k, nf, nr = struct.unpack_from("<Qii", img.raw, 0)
+        assert (nf, nr) == (2, 4)
+        return k
+
+    k0 = key(ds, me, 1 << 30)
+    assert key(ds, me, 1 << 30) == k0
+    assert key(ds, me, (1 << 30) + 256) != k0
+    other = R.MEParams(check="rmc").c()
+    assert key(ds, other, 1 << 30) != k0
+    ds2 = _descs(R, shapes, nrefs)
+    ds2[1].out = ds2[1].out + 256
+    assert key(ds2, me, 1 << 30) != k0
+    ds3 = _descs(R, shapes, nrefs)
+    ds3[0].reserved = 7           # not part of the key
+    assert key(ds3, me, 1 << 30) == k0
+    # errors: image too small, misaligned workspace
+    assert lib.rfsr_batch_write_tables(ds, 2, ctypes.byref(me), ctypes.c_void_p(1 << 30), img, tb - 1) == -1
+    assert lib.rfsr_batch_write_tables(ds, 2, ctypes.byref(me), ctypes.c_void_p((1 << 30) + 8), img, tb) == -3
+
+
+def test_reconstruct_batch_rejects_bad_arguments(R):
+    lib = R.lib()
+    P = ctypes.c_void_p
+    me, fsr = R.MEParams().c(), R.FSRParams().c()
+    ds = _descs(R, [(64, 64)], [2])
+    need = lib.rfsr_batch_workspace_bytes(ds, 1, ctypes.byref(me), ctypes.byref(fsr))
+    ws, tab = P(1 << 32), P(1 << 33)
+    call = lambda d=ds, n=1, t=tab, w=ws, nb=need, ev=None, m=me, f=fsr: lib.rfsr_reconstruct_batch(
+        d, n, ctypes.byref(m), ctypes.byref(f), t, ev, w, nb, None)
+    assert call(t=None) == -1
+    assert call(t=P((1 << 33) + 64)) == -1
+    assert call(w=None) == -3
+    assert call(nb=need - 1) == -3
+    assert call(w=P((1 << 32) + 16)) == -3
+    assert call(n=0) == -1
+    assert call(ev=(P * 4)(1, 2, None, 4)) == -1
+    bad_me = R.MEParams(search=16).c()
+    assert call(m=bad_me) == -1
+    bad_fsr = R.FSRParams(iters=-1).c()
+    assert call(f=bad_fsr) == -1
