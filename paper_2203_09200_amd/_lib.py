@@ -392,10 +392,13 @@ class Batch:
     workspace: optional uint8 device tensor (256-byte aligned, at least
     `Batch.workspace_bytes(frames)`), which batches that never run at the
     same time may share.
+    stream: if given, the job tables are uploaded asynchronously on it (from
+    pinned memory) and the host does not wait; run the batch on the same
+    stream.  Otherwise the upload completes before the constructor returns.
     """
 
     def __init__(self, frames, me: MEParams | None = None, fsr: FSRParams | None = None,
-                 workspace: torch.Tensor | None = None):
+                 workspace: torch.Tensor | None = None, stream=None):
         if not frames:
             raise RfsrError("Batch: no frames")
         self.frames = list(frames)
@@ -418,11 +421,17 @@ class Batch:
         image = torch.empty(tb, dtype=torch.uint8, pin_memory=True)
         _check(L.rfsr_batch_write_tables(self.descs, self.n, ctypes.byref(self._mc), _ptr(workspace),
                                          _ptr(image), tb), "rfsr_batch_write_tables")
-        self.tables = torch.empty(tb, dtype=torch.uint8, device=self.device)
+        if stream is None:
+            self.tables = torch.empty(tb, dtype=torch.uint8, device=self.device)
+            self.tables.copy_(image)
+            torch.cuda.current_stream(self.device).synchronize()
+        else:
+            with torch.cuda.stream(stream):
+                self.tables = torch.empty(tb, dtype=torch.uint8, device=self.device)
+                self.tables.copy_(image, non_blocking=True)
+            self._image = image     # keep the pinned source alive with the batch
         if self.tables.data_ptr() % 256:
             raise RfsrError("Batch: job-table allocation is not 256-byte aligned")
-        self.tables.copy_(image)
-        torch.cuda.current_stream(self.device).synchronize()
 
     @staticmethod
     def workspace_bytes(frames, me: MEParams | None = None, fsr: FSRParams | None = None) -> int:

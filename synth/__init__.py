@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "seed_for", "fixed_mask", "dynamic_masks", "mask_sequence",
     "bandlimited_noise", "video_translate_edges", "video_regions",
-    "measured", "workload_c1", "workload_c2",
+    "measured", "workload_c1", "workload_c2", "C4_SIZES", "workload_c4",
 ]
 
 BASE_SEED = 220309200
@@ -196,3 +196,21 @@ def workload_c2(n: int = 16, h: int = 1080, w: int = 1920, seed: int | None = No
     frames = video_regions(n, h, w, rng)
     masks = mask_sequence("dynamic", n, h, w, rng)
     return frames, masks
+
+
+# Batched multi-stream configuration: 16 CIF, 16 720p, 12 1080p and 4 2160p
+# streams (H, W).
+C4_SIZES = [(288, 352)] * 16 + [(720, 1280)] * 16 + [(1080, 1920)] * 12 + [(2160, 3840)] * 4
+
+
+def workload_c4(n: int = 8, sizes=None):
+    """Multi-stream workload: one (frames, masks) pair per stream, the 1080p
+    generator at each stream's size, n frames each; even stream index ->
+    fixed mask, odd -> dynamic.  Stream s uses seed_for(4, s)."""
+    out = []
+    for s, (h, w) in enumerate(C4_SIZES if sizes is None else sizes):
+        rng = np.random.default_rng(seed_for(4, s))
+        frames = video_regions(n, h, w, rng)
+        masks = mask_sequence("fixed" if s % 2 == 0 else "dynamic", n, h, w, rng)
+        out.append((frames, masks))
+    return out

@@ -50,3 +50,18 @@ def test_generators_seeded_and_shaped():
     f, m = synth.workload_c2(n=3, h=96, w=160)
     assert f.shape == (3, 96, 160) and m.shape == (3, 96, 160)
     assert f.std() > 5
+
+
+def test_multistream_workload_sizes_and_masks():
+    assert len(synth.C4_SIZES) == 48
+    assert sum(h * w for h, w in synth.C4_SIZES) == 74_428_416
+    small = [(32, 48), (16, 24), (24, 16)]
+    ws = synth.workload_c4(n=4, sizes=small)
+    for s, ((f, m), (h, w)) in enumerate(zip(ws, small)):
+        assert f.shape == m.shape == (4, h, w)
+        cells = m.reshape(4, h // 2, 2, w // 2, 2).sum(axis=(2, 4))
+        assert (cells == 1).all()
+        if s % 2 == 0:   # fixed
+            assert (m == m[0]).all()
+        else:            # dynamic: every position once in four frames
+            assert (m.sum(axis=0) == 1).all()
