@@ -99,7 +99,25 @@ typedef struct {
     double rho;          /* 0 < rho <= 1                                      */
     double gamma;        /* 0 < gamma < 2                                     */
     double proj_weight;  /* >= 0, weight of projected samples                 */
+    int32_t precision;   /* rfsr_precision of the block DFT (0 = float64)     */
+    int32_t reserved;    /* set to 0                                          */
 } rfsr_fsr_params;
+
+/* Arithmetic of the block DFT that starts FSR (R = DFT(w s), W = DFT(w));
+ * the iterations are float64 in every case.
+ *   FP64     float64 FFT on the vector ALU (the reference precision).
+ *   BF16X3   two 32x32 GEMM stages on the matrix cores (MFMA), operands
+ *            split as hi + lo in bfloat16, products hi*hi + hi*lo + lo*hi
+ *            accumulated in float32.
+ *   FP16X3   the same with float16 operands.
+ * The 16-bit forms trade DFT accuracy (float32 accumulation, ~2^-16 / ~2^-22
+ * operand splits) for matrix-core throughput; they are not bit-compatible
+ * with FP64 and exist to quantify that trade. */
+typedef enum {
+    RFSR_PREC_FP64 = 0,
+    RFSR_PREC_BF16X3 = 1,
+    RFSR_PREC_FP16X3 = 2
+} rfsr_precision;
 
 /* Indices into the optional counters array of rfsr_motion_check. */
 enum {

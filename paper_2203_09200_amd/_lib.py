@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librfsr.so")
 
 CHECKS = {"none": 0, "rme": 1, "rmc": 2, "frmc": 3, "nnc": 4, "nnc_frmc": 5}
 OVERWRITE = {"dfsr": 0, "rfsr": 1}
+PRECISION = {"fp64": 0, "bf16x3": 1, "fp16x3": 2}
 NCOUNTERS = 4
 COUNTER_NAMES = ("forward_costs", "check_costs", "checked_pixels", "accepted")
 
@@ -35,7 +36,8 @@ class _FSRParams(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("overwrite", ctypes.c_int32),
                 ("rho", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("proj_weight", ctypes.c_double)]
+                ("proj_weight", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 @dataclass
@@ -60,10 +62,11 @@ class FSRParams:
     overwrite: str = "dfsr"
     block: int = 4
     support: int = 32
+    precision: str = "fp64"     # block DFT: "fp64", "bf16x3" or "fp16x3" (matrix cores)
 
     def c(self) -> _FSRParams:
         return _FSRParams(self.block, self.support, self.iters, OVERWRITE[self.overwrite],
-                          self.rho, self.gamma, self.proj_weight)
+                          self.rho, self.gamma, self.proj_weight, PRECISION[self.precision], 0)
 
 
 class FrameDesc(ctypes.Structure):

@@ -14,7 +14,7 @@ using namespace rfsr;
 
 namespace {
 
-constexpr int32_t kVersion = 10100;   // 1.1.0
+constexpr int32_t kVersion = 10200;   // 1.2.0
 constexpr int kMaxBatch = 4096;
 
 rfsr_status from_hip(hipError_t e) { return e == hipSuccess ? RFSR_OK : RFSR_EDEVICE; }
@@ -44,6 +44,7 @@ rfsr_status check_fsr(const rfsr_fsr_params* p) {
     if (!(p->proj_weight >= 0.0) || !isfinite(p->proj_weight)) return RFSR_EINVAL;
     if (p->overwrite != RFSR_DFSR && p->overwrite != RFSR_RFSR) return RFSR_EINVAL;
     if (p->block < 1 || p->support < p->block) return RFSR_EINVAL;
+    if (p->precision < RFSR_PREC_FP64 || p->precision > RFSR_PREC_FP16X3) return RFSR_EINVAL;
     if (p->block != kBlock || p->support != kSupport) return RFSR_EUNSUPPORTED;
     return RFSR_OK;
 }

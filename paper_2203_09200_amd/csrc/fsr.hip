@@ -175,6 +175,138 @@ __device__ __forceinline__ double pack_energy(double e, uint32_t code) {
 
 constexpr int kPlane = 33;                       // padded row length of a transpose plane
 
+// ------------------------------------------------------------------------
+// Block DFT on the matrix cores (precision study): Z = F X F with
+// F[k][m] = exp(-2 pi i k m / 32), as two 32x32x32 real GEMM stages per
+// input (w*s and w) on v_mfma_f32_32x32x16_{bf16,f16}.  Every operand is
+// split as x = hi + lo in the 16-bit type and a product is accumulated as
+// hi*hi + hi*lo + lo*hi in float32 (lo*lo dropped).
+//
+// Lane layouts of the 32x32x16 MFMA (l = lane, half = l / 32):
+//   A[i][k]: lane i + 32 half holds k = 8 half + t, t = 0..7
+//   B[k][j]: lane j + 32 half holds k = 8 half + t
+//   D[i][j]: lane j + 32 half, register r holds i = 8 (r / 4) + 4 half + r % 4
+// The K index is summed over, so each stage numbers its K slots to match the
+// registers the lane already holds, and stage 1 computes the frequencies in
+// the order sigma(j) = 4 (j / 8) + j % 4 + 16 ((j / 4) % 2), which makes the
+// stage-2 result land in the iteration layout (lane (h, c) holds
+// k = (r + 16 h, c) in register r) with no data movement between stages.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int PREC> struct Mma;
+template <> struct Mma<RFSR_PREC_BF16X3> {
+    using V = bf16x8;
+    using E = __bf16;
+    static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mma<RFSR_PREC_FP16X3> {
+    using V = f16x8;
+    using E = _Float16;
+    static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <int PREC>
+struct Split {   // x = hi + lo, eight K slots
+    typename Mma<PREC>::V hi, lo;
+};
+
+template <int PREC>
+__device__ __forceinline__ void split_into(Split<PREC>& s, int t, float x) {
+    using E = typename Mma<PREC>::E;
+    const E hi = (E)x;
+    s.hi[t] = hi;
+    s.lo[t] = (E)(x - (float)hi);
+}
+
+// acc += a * b with split operands.
+template <int PREC>
+__device__ __forceinline__ f32x16 mma3(const Split<PREC>& a, const Split<PREC>& b, f32x16 acc) {
+    acc = Mma<PREC>::mma(a.hi, b.hi, acc);
+    acc = Mma<PREC>::mma(a.hi, b.lo, acc);
+    return Mma<PREC>::mma(a.lo, b.hi, acc);
+}
+
+template <int PREC>
+__device__ __forceinline__ Split<PREC> negate(const Split<PREC>& a) {
+    Split<PREC> r;
+    r.hi = -a.hi;
+    r.lo = -a.lo;
+    return r;
+}
+
+// DFT of the gathered support.  In: xs[i] = w*s, xw[i] = w at (m = i + 16 h,
+// n = c).  Out (iteration layout, float64): R = DFT(w*s), W = DFT(w).
+// tw: exp(-2 pi i t / 32), t = 0..31, (re, im) interleaved.
+template <int PREC>
+__device__ __forceinline__ void dft_mfma(const double (&xs)[16], const double (&xw)[16], int lane,
+                                         const double* tw, double (&Rr)[16], double (&Ri)[16],
+                                         double (&Wr)[16], double (&Wi)[16]) {
+    const int j = lane & 31, half = lane >> 5;
+    const int fj = 4 * (j >> 3) + (j & 3) + 16 * ((j >> 2) & 1);   // sigma(j)
+
+    // stage 1: D1[n][j] = sum_m X[m][n] F[sigma(j)][m]; A = X^T (K slot t of
+    // k-block kb is m = 16 half + 8 kb + t: the lane's own register 8 kb + t)
+    f32x16 ysr = {}, ysi = {}, ywr = {}, ywi = {};
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        Split<PREC> as, aw, bre, bim;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            split_into(as, t, (float)xs[8 * kb + t]);
+            split_into(aw, t, (float)xw[8 * kb + t]);
+            const int m = 16 * half + 8 * kb + t;
+            const int e = (m * fj) & 31;
+            split_into(bre, t, (float)tw[2 * e]);
+            split_into(bim, t, (float)tw[2 * e + 1]);
+        }
+        ysr = mma3(as, bre, ysr);
+        ysi = mma3(as, bim, ysi);
+        ywr = mma3(aw, bre, ywr);
+        ywi = mma3(aw, bim, ywi);
+    }
+
+    // stage 2: Z[sigma(i)][k2] = sum_n Y[sigma(i)][n] F[n][k2]; A = Y (the
+    // lane's D1 registers 8 kb + t hold n = 16 kb + 8 (t / 4) + 4 half + t % 4)
+    //   Zr = Yr C + Yi S,  Zi = Yi C - Yr S   (C = cos, S = sin of 2 pi n k2 / 32)
+    f32x16 zsr = {}, zsi = {}, zwr = {}, zwi = {};
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        Split<PREC> c2, s2, a_sr, a_si, a_wr, a_wi;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int n = 16 * kb + 8 * (t >> 2) + 4 * half + (t & 3);
+            const int e = (n * j) & 31;
+            split_into(c2, t, (float)tw[2 * e]);
+            split_into(s2, t, -(float)tw[2 * e + 1]);
+            split_into(a_sr, t, ysr[8 * kb + t]);
+            split_into(a_si, t, ysi[8 * kb + t]);
+            split_into(a_wr, t, ywr[8 * kb + t]);
+            split_into(a_wi, t, ywi[8 * kb + t]);
+        }
+        zsr = mma3(a_sr, c2, zsr);
+        zsr = mma3(a_si, s2, zsr);
+        zsi = mma3(a_si, c2, zsi);
+        zsi = mma3(negate(a_sr), s2, zsi);
+        zwr = mma3(a_wr, c2, zwr);
+        zwr = mma3(a_wi, s2, zwr);
+        zwi = mma3(a_wi, c2, zwi);
+        zwi = mma3(negate(a_wr), s2, zwi);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        Rr[r] = zsr[r];
+        Ri[r] = zsi[r];
+        Wr[r] = zwr[r];
+        Wi[r] = zwi[r];
+    }
+}
+
 }  // namespace
 
 __global__ void fsr_tables_kernel(FsrTables* t, double rho) {
@@ -196,6 +328,7 @@ __global__ void fsr_tables_kernel(FsrTables* t, double rho) {
 // One workgroup per block of the flat block index over all the frames of
 // `js`.  (A loop over several blocks per workgroup lets the compiler hoist
 // per-lane tables out of it and spill; launches are cheap by comparison.)
+template <int PREC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void fsr_block_kernel(
     Jobs<FrameJob> js, int total, const FsrTables* __restrict__ tab, int K, double gamma,
     double projw, int overwrite) {
@@ -256,52 +389,57 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             }
         }
 
-        // 2. DFT along the support rows m (per column), transpose, DFT along n.
-        double* pl = reinterpret_cast<double*>(smem);   // one 32 x 33 plane at a time
-        fft32_pair(zr, zi, h, tw);                      // register k': Y[k1 = 2k'+h][n = c]
-#pragma unroll
-        for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zr[k];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 16; ++i) zr[i] = pl[c * kPlane + i + 16 * h];   // row k1 = c, n = i + 16h
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zi[k];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 16; ++i) zi[i] = pl[c * kPlane + i + 16 * h];
-        fft32_pair(zr, zi, h, tw);                      // register j: Z[k1 = c][k2 = 2j + h]
-
-        // 3. split Z = DFT(w s) + i DFT(w) using Z(-k), into the iteration layout
-        //    k = (j + 16 h, c).
         double Rr[16], Ri[16], Wr[16], Wi[16];
-        {
-            const int nc = (32 - c) & 31;
+        if constexpr (PREC != RFSR_PREC_FP64) {
+            __syncthreads();   // s_tw
+            dft_mfma<PREC>(zr, zi, lane, s_tw, Rr, Ri, Wr, Wi);
+        } else {
+            // 2. DFT along the support rows m (per column), transpose, DFT along n.
+            double* pl = reinterpret_cast<double*>(smem);   // one 32 x 33 plane at a time
+            fft32_pair(zr, zi, h, tw);                      // register k': Y[k1 = 2k'+h][n = c]
+#pragma unroll
+            for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zr[k];
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zr[j];
+            for (int i = 0; i < 16; ++i) zr[i] = pl[c * kPlane + i + 16 * h];   // row k1 = c, n = i + 16h
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
-                Wr[j] = pl[k1 * kPlane + c];      // Z.re(k)
-                Wi[j] = pl[nk1 * kPlane + nc];    // Z.re(-k)
+            for (int k = 0; k < 16; ++k) pl[(2 * k + h) * kPlane + c] = zi[k];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) zi[i] = pl[c * kPlane + i + 16 * h];
+            fft32_pair(zr, zi, h, tw);                      // register j: Z[k1 = c][k2 = 2j + h]
+
+            // 3. split Z = DFT(w s) + i DFT(w) using Z(-k), into the iteration layout
+            //    k = (j + 16 h, c).
+            {
+                const int nc = (32 - c) & 31;
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zr[j];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
+                    Wr[j] = pl[k1 * kPlane + c];      // Z.re(k)
+                    Wi[j] = pl[nk1 * kPlane + nc];    // Z.re(-k)
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zi[j];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
+                    const double ar = Wr[j], br = Wi[j];                                 // Z.re(k), Z.re(-k)
+                    const double ai = pl[k1 * kPlane + c], bim = pl[nk1 * kPlane + nc];  // Z.im(k), Z.im(-k)
+                    Rr[j] = 0.5 * (ar + br);
+                    Ri[j] = 0.5 * (ai - bim);
+                    Wr[j] = 0.5 * (ai + bim);
+                    Wi[j] = 0.5 * (br - ar);
+                }
+                __syncthreads();
             }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < 16; ++j) pl[c * kPlane + 2 * j + h] = zi[j];
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int k1 = j + 16 * h, nk1 = (32 - k1) & 31;
-                const double ar = Wr[j], br = Wi[j];                                 // Z.re(k), Z.re(-k)
-                const double ai = pl[k1 * kPlane + c], bim = pl[nk1 * kPlane + nc];  // Z.im(k), Z.im(-k)
-                Rr[j] = 0.5 * (ar + br);
-                Ri[j] = 0.5 * (ai - bim);
-                Wr[j] = 0.5 * (ai + bim);
-                Wi[j] = 0.5 * (br - ar);
-            }
-            __syncthreads();
         }
         double2* T = reinterpret_cast<double2*>(smem);
 #pragma unroll
@@ -391,7 +529,10 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
                       const FsrTables* tables, hipStream_t s) {
     if (total_blocks <= 0) return hipSuccess;
     const size_t shmem = sizeof(float4) * (size_t)p.iters;
-    hipLaunchKernelGGL(fsr_block_kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
+    auto kernel = fsr_block_kernel<RFSR_PREC_FP64>;
+    if (p.precision == RFSR_PREC_BF16X3) kernel = fsr_block_kernel<RFSR_PREC_BF16X3>;
+    else if (p.precision == RFSR_PREC_FP16X3) kernel = fsr_block_kernel<RFSR_PREC_FP16X3>;
+    hipLaunchKernelGGL(kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
                        p.gamma, p.proj_weight, p.overwrite);
     return hipGetLastError();
 }
