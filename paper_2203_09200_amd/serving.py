@@ -482,6 +482,8 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--pool", type=int, default=8, help="distinct synthetic frames per size and mask kind")
+    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3"], default="fp64",
+                    help="block DFT arithmetic of the batched server (the plain loop stays fp64)")
     a = ap.parse_args(argv)
 
     import numpy as np
@@ -518,14 +520,15 @@ def main(argv=None):
         fm, mm = pool[(*sizes[s], kinds[s])]
         return fm[(i + offs[s]) % a.pool], mm[(i + offs[s]) % a.pool]
 
-    me, fsr = R.MEParams(), R.FSRParams(iters=a.iters)
+    me = R.MEParams()
     px_of = lambda r: r.out.numel()
     results = {}
-    modes = [("batched", "batch", a.max_batch, a.max_inflight)]
+    modes = [("batched", "batch", a.max_batch, a.max_inflight, a.precision)]
     if not a.no_plain:
-        modes.append(("plain", "frame", 1, 1))
+        modes.append(("plain", "frame", 1, 1, "fp64"))
     budget = int(a.budget_gib * 2**30)
-    for name, mode, mb, mi in modes:
+    for name, mode, mb, mi, prec in modes:
+        fsr = R.FSRParams(iters=a.iters, precision=prec)
         ex = GpuExecutor(me, fsr, dev, mode=mode, max_inflight=mi)
         # warm-up outside the trace: four frames per stream (kernels loaded, allocator primed)
         warm_srv = Server(ex, budget, max_batch=mb, max_inflight=mi)
@@ -549,7 +552,8 @@ def main(argv=None):
     out = {"metric": "serving: HR Mpix/s sustained and p50/p99 frame latency (arrival -> result on device)",
            "streams": a.streams, "frames_per_stream": a.frames, "fps": a.fps * a.load,
            "sizes": {f"{h}x{w}": sizes.count((h, w)) for h, w in SIZES},
-           "iters": a.iters, "max_batch": a.max_batch, "max_inflight": a.max_inflight,
+           "iters": a.iters, "precision": a.precision, "max_batch": a.max_batch,
+           "max_inflight": a.max_inflight,
            "budget_gib": a.budget_gib, **results}
     print(json.dumps(out))
     return 0
