@@ -17,6 +17,7 @@ Modules
   fsr         Sec. 2.1 / Sec. 3.2: block-wise FSR with concealed weighting 0.
   frame       Fig. 1 order (ME -> check -> projection -> FSR) for one frame,
               the causal recursion over a sequence, PSNR (Sec. 4).
+  quality     mean SSIM reported beside PSNR (Sec. 4).
 
 Readings of points the paper leaves open are listed in each module header.
 """
@@ -28,6 +29,7 @@ from .projection import project
 from .fsr import (rho_table, fsr_spatial, fsr_spectral, gather_supports, fsr_frame)
 from .frame import (MEParams, FSRParams, reconstruct_frame, reconstruct_sequence,
                     quantize, psnr)
+from .quality import gaussian_window, ssim, ssim_map, ssim_bruteforce
 
 __all__ = [
     "template_offsets", "cost_at", "reverse_cost_at", "n_map", "forward_me",
@@ -35,5 +37,5 @@ __all__ = [
     "rmc_accept", "median3x3", "nnc_accept", "motion_check", "CHECKS", "project",
     "rho_table", "fsr_spatial", "fsr_spectral", "gather_supports", "fsr_frame",
     "MEParams", "FSRParams", "reconstruct_frame", "reconstruct_sequence",
-    "quantize", "psnr",
+    "quantize", "psnr", "gaussian_window", "ssim", "ssim_map", "ssim_bruteforce",
 ]
