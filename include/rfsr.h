@@ -253,6 +253,26 @@ rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n,
                                    const void* job_tables, void* const* stage_events,
                                    void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------- quality ---
+ * Reconstruction quality as evaluated in Sec. 4: PSNR and mean SSIM of a
+ * reconstruction against the ground truth with a border of `border` pixels
+ * omitted (the paper omits 40) and the reconstruction clipped to [0, 255]
+ * (not rounded).  SSIM as defined by Wang et al. (IEEE TIP 2004, which the
+ * paper cites): 11x11 Gaussian window of standard deviation 1.5, unit sum,
+ * C1 = (0.01*255)^2, C2 = (0.03*255)^2, averaged over every window position
+ * inside the cropped frame.  Accumulation in float64, reduced in a fixed
+ * order (the result does not depend on scheduling).
+ *   ref     uint8 H x W ground truth (device)
+ *   test    float32 H x W reconstruction (device), same pitch
+ *   result  DEVICE double[2] out: { PSNR in dB (+inf if identical), mean SSIM }
+ * H and W need not be multiples of 4; the cropped frame must be >= 11 x 11.
+ * Errors: RFSR_EINVAL (null pointer, border < 0), RFSR_ESHAPE (sizes, pitch,
+ * cropped frame < 11 x 11), RFSR_EWORKSPACE, RFSR_EDEVICE. */
+size_t rfsr_quality_workspace_bytes(int32_t H, int32_t W, int32_t border);
+rfsr_status rfsr_quality(const uint8_t* ref, const float* test, int32_t H, int32_t W,
+                         int64_t pitch, int32_t border, double* result,
+                         void* workspace, size_t ws_bytes, void* stream);
+
 /* Timing events for stage_events and benchmarks (thin wrappers of HIP
  * events).  rfsr_event_elapsed_ms waits for `stop`. */
 rfsr_status rfsr_event_create(void** event);

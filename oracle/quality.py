@@ -27,9 +27,7 @@ K1, K2, L = 0.01, 0.03, 255.0
 def gaussian_window(size: int = 11, sigma: float = 1.5) -> np.ndarray:
     """(size, size) Gaussian weights, unit sum (outer product of the 1-D
     normalised Gaussian, which is the same as normalising the 2-D one)."""
-    x = np.arange(size, dtype=np.float64) - (size - 1) / 2.0
-    g = np.exp(-x ** 2 / (2.0 * sigma ** 2))
-    g /= g.sum()
+    g = _gauss1d(size, sigma)
     return np.outer(g, g)
 
 
@@ -41,16 +39,24 @@ def _prepare(ref, test, border):
     return ref[sl], test[sl]
 
 
-def _filter_valid(img: np.ndarray, win: np.ndarray) -> np.ndarray:
-    """Weighted sums sum_{u,v} win[u,v] img[y+u, x+v] over every window that
-    fits in the image (a library primitive: sliding windows + tensordot)."""
-    v = np.lib.stride_tricks.sliding_window_view(img, win.shape)
-    return np.tensordot(v, win, axes=([2, 3], [0, 1]))
+def _gauss1d(size: int, sigma: float) -> np.ndarray:
+    x = np.arange(size, dtype=np.float64) - (size - 1) / 2.0
+    g = np.exp(-x ** 2 / (2.0 * sigma ** 2))
+    return g / g.sum()
+
+
+def _filter_valid(img: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """Weighted sums sum_{u,v} g[u] g[v] img[y+u, x+v] over every window that
+    fits in the image.  The window is the outer product g g^T, so the double
+    sum is a 1-D weighted sum along the rows followed by one along the
+    columns (sliding windows + tensordot as the library primitive)."""
+    rows = np.tensordot(np.lib.stride_tricks.sliding_window_view(img, g.size, axis=1), g, axes=([2], [0]))
+    return np.tensordot(np.lib.stride_tricks.sliding_window_view(rows, g.size, axis=0), g, axes=([2], [0]))
 
 
 def ssim_map(ref, test, border: int = 40, size: int = 11, sigma: float = 1.5) -> np.ndarray:
     x, y = _prepare(ref, test, border)
-    w = gaussian_window(size, sigma)
+    w = _gauss1d(size, sigma)
     C1, C2 = (K1 * L) ** 2, (K2 * L) ** 2
     mx, my = _filter_valid(x, w), _filter_valid(y, w)
     sxx = _filter_valid(x * x, w) - mx * mx

@@ -7,8 +7,9 @@ include/rfsr.h); this package is its Python binding.
 """
 from ._lib import (CHECKS, COUNTER_NAMES, Batch, BatchFrame, Event, FrameDesc, FSRParams, MEParams,
                    RfsrError, Sequence, StreamSet, Workspace, fsr_blocks, lib, motion_check,
-                   reconstruct_frame, workspace_bytes, LIB_PATH)
+                   quality, quality_async, reconstruct_frame, workspace_bytes, LIB_PATH)
 
 __all__ = ["CHECKS", "COUNTER_NAMES", "Batch", "BatchFrame", "Event", "FrameDesc", "FSRParams",
            "MEParams", "RfsrError", "Sequence", "StreamSet", "Workspace", "fsr_blocks", "lib",
-           "motion_check", "reconstruct_frame", "workspace_bytes", "LIB_PATH"]
+           "motion_check", "quality", "quality_async", "reconstruct_frame", "workspace_bytes",
+           "LIB_PATH"]

@@ -119,6 +119,11 @@ def lib():
     L.rfsr_reconstruct_batch.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32,
                                          ctypes.POINTER(_MEParams), ctypes.POINTER(_FSRParams), _P,
                                          ctypes.POINTER(_P), _P, ctypes.c_size_t, _P]
+    L.rfsr_quality_workspace_bytes.restype = ctypes.c_size_t
+    L.rfsr_quality_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.rfsr_quality.restype = _STATUS
+    L.rfsr_quality.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P,
+                               ctypes.c_size_t, _P]
     L.rfsr_event_create.restype = _STATUS
     L.rfsr_event_create.argtypes = [ctypes.POINTER(_P)]
     L.rfsr_event_destroy.restype = _STATUS
@@ -291,6 +296,33 @@ def reconstruct_frame(cur, cur_mask, refs=(), me: MEParams | None = None,
                                       _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "rfsr_reconstruct_frame")
     return out, out_u8
+
+
+def quality_async(ref, test, border: int = 40, result=None, workspace: Workspace | None = None, stream=None):
+    """PSNR and mean SSIM (Sec. 4) of `test` (float32 device plane) against
+    `ref` (uint8 device plane), computed on the device.  Returns a float64
+    device tensor (psnr, ssim); nothing is synchronised."""
+    _plane(ref, torch.uint8, "ref")
+    H, W = ref.shape
+    _plane(test, torch.float32, "test", (H, W))
+    if ref.stride(0) != test.stride(0):
+        raise RfsrError("quality: ref and test must share the row pitch")
+    n = lib().rfsr_quality_workspace_bytes(H, W, border)
+    if n == 0:
+        raise RfsrError(f"quality: {H}x{W} with border {border} leaves less than one 11x11 window")
+    ws = _ws(workspace, ref.device, n)
+    if result is None:
+        result = torch.empty(2, dtype=torch.float64, device=ref.device)
+    st = lib().rfsr_quality(_ptr(ref), _ptr(test), H, W, ref.stride(0), border, _ptr(result), _ptr(ws),
+                            ws.numel(), _stream(stream))
+    _check(st, "rfsr_quality")
+    return result
+
+
+def quality(ref, test, border: int = 40, workspace: Workspace | None = None, stream=None):
+    """(psnr, mean ssim) as Python floats (waits for the device)."""
+    r = quality_async(ref, test, border, workspace=workspace, stream=stream).cpu()
+    return float(r[0]), float(r[1])
 
 
 class Event:

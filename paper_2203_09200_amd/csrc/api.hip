@@ -511,6 +511,26 @@ rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n, con
     return from_hip(e);
 }
 
+size_t rfsr_quality_workspace_bytes(int32_t H, int32_t W, int32_t border) {
+    if (H <= 0 || W <= 0 || H > kMaxDim || W > kMaxDim || border < 0) return 0;
+    if ((int64_t)H - 2 * (int64_t)border < 11 || (int64_t)W - 2 * (int64_t)border < 11) return 0;
+    return align256(2 * sizeof(double) * (size_t)quality_tiles(H, W, border));
+}
+
+rfsr_status rfsr_quality(const uint8_t* ref, const float* test, int32_t H, int32_t W, int64_t pitch,
+                         int32_t border, double* result, void* workspace, size_t ws_bytes, void* stream) {
+    if (!ref || !test || !result) return RFSR_EINVAL;
+    if (border < 0) return RFSR_EINVAL;
+    if (H <= 0 || W <= 0 || H > kMaxDim || W > kMaxDim || pitch < W || pitch > (int64_t)1 << 30)
+        return RFSR_ESHAPE;
+    const size_t need = rfsr_quality_workspace_bytes(H, W, border);
+    if (need == 0) return RFSR_ESHAPE;   // cropped frame smaller than one window
+    rfsr_status st = check_ws(workspace, ws_bytes, need);
+    if (st != RFSR_OK) return st;
+    return from_hip(launch_quality(ref, test, H, W, pitch, border, static_cast<double*>(workspace), result,
+                                   static_cast<hipStream_t>(stream)));
+}
+
 rfsr_status rfsr_event_create(void** event) {
     if (!event) return RFSR_EINVAL;
     hipEvent_t ev;

@@ -207,4 +207,10 @@ hipError_t launch_motion(const Jobs<RefJob>& js, int total_tiles, int total_px, 
                          const rfsr_me_params& me, unsigned long long* counters, hipStream_t s);
 bool check_needs_windows(int check);
 
+// Quality (PSNR, mean SSIM) of a reconstruction: `partial` holds
+// 2 * quality_tiles(H, W, border) doubles; `result` receives (psnr, ssim).
+int quality_tiles(int H, int W, int border);
+hipError_t launch_quality(const uint8_t* ref, const float* test, int H, int W, int64_t pitch, int border,
+                          double* partial, double* result, hipStream_t s);
+
 }  // namespace rfsr

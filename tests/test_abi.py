@@ -217,3 +217,23 @@ def test_reconstruct_batch_rejects_bad_arguments(R):
     assert call(m=bad_me) == -1
     bad_fsr = R.FSRParams(iters=-1).c()
     assert call(f=bad_fsr) == -1
+
+
+def test_quality_validation(R):
+    lib = R.lib()
+    P = ctypes.c_void_p
+    fake = P(4096)
+    assert lib.rfsr_quality_workspace_bytes(100, 100, 40) > 0
+    assert lib.rfsr_quality_workspace_bytes(90, 100, 40) == 0        # 10 rows left < 11
+    assert lib.rfsr_quality_workspace_bytes(11, 11, 0) > 0
+    assert lib.rfsr_quality_workspace_bytes(100, 100, -1) == 0
+    n = lib.rfsr_quality_workspace_bytes(100, 100, 40)
+    call = lambda ref=fake, H=100, W=100, pitch=100, border=40, res=fake, ws=fake, nb=n: lib.rfsr_quality(
+        ref, fake, H, W, pitch, border, res, ws, nb, None)
+    assert call(ref=None) == -1
+    assert call(res=None) == -1
+    assert call(border=-2) == -1
+    assert call(H=90) == -2
+    assert call(pitch=99) == -2
+    assert call(ws=None) == -3
+    assert call(nb=n - 1) == -3
