@@ -195,6 +195,59 @@ def fsr_blocks_out(values, cls, blocks, B=4, M=32, rho=0.7, gamma=0.5, K=100,
     return np.concatenate(outs), np.concatenate(gaps)
 
 
+def fsr_frame_concealed(values, cls, delta, B=4, M=32, rho=0.7, gamma=0.5, K=100,
+                        proj_weight=1.0, overwrite="dfsr", given=None):
+    """FSR with a non-zero concealed weighting `delta` (the setting of the
+    FSR literature that Sec. 4 sets to zero).  Blocks are reconstructed one
+    after another in raster order (block rows top to bottom, each left to
+    right); a pixel of an earlier block that had no sample (class 0) enters
+    the supports of later blocks as a sample with weight delta * rho^dist
+    and its reconstructed value (the block output, float).  delta = 0 is
+    `fsr_frame`.  given: optional (H, W) reconstruction whose values the
+    concealed pixels take instead of this function's own outputs (to check
+    another implementation block by block on its own upstream values).
+    Returns (out (H, W) float64, gaps (H/B, W/B)) as `fsr_frame`.
+
+    Reading: the reconstructed value is the unclamped model output; measured
+    and projected pixels keep their own weights and values."""
+    H, W = values.shape
+    v = np.where(cls > 0, values, 0.0).astype(np.float64)
+    a = class_weight(cls, proj_weight)          # concealed pixels get `delta` below
+    out = np.zeros((H, W))
+    gaps = np.zeros((H // B, W // B))
+    tab = rho_table(rho, M)
+    for bi in range(H // B):
+        for bj in range(W // B):
+            blk = np.array([[bi, bj]])
+            s, aw = _gather(v, a, blk, B, M)
+            c, _, g, _ = fsr_spatial(s, aw * tab[None], gamma, K, track_gaps=True)
+            gaps[bi, bj] = g[0]
+            o = synthesize(c, B)[0]
+            sl = (slice(B * bi, B * bi + B), slice(B * bj, B * bj + B))
+            cb, vb = cls[sl], values[sl]
+            keep = (cb == 1) if overwrite == "dfsr" else (cb >= 1)
+            o[keep] = vb[keep]
+            out[sl] = o
+            unknown = cb == 0
+            src = o if given is None else np.asarray(given, np.float64)[sl]
+            v[sl][unknown] = src[unknown]        # concealed from now on
+            a[sl][unknown] = delta
+    return out, gaps
+
+
+def _gather(v, a, blocks, B, M):
+    """Samples v and weights a on the supports of `blocks` (zero outside)."""
+    o = (M - B) // 2
+    pad = ((o, M - B - o + B), (o, M - B - o + B))
+    vp, ap = np.pad(v, pad), np.pad(a, pad)
+    s = np.empty((len(blocks), M, M))
+    aw = np.empty((len(blocks), M, M))
+    for i, (bi, bj) in enumerate(blocks):
+        s[i] = vp[B * bi:B * bi + M, B * bj:B * bj + M]
+        aw[i] = ap[B * bi:B * bi + M, B * bj:B * bj + M]
+    return s, aw
+
+
 def all_blocks(H, W, B=4):
     bi, bj = np.mgrid[0:H // B, 0:W // B]
     return np.stack([bi.ravel(), bj.ravel()], axis=1)

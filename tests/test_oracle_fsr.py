@@ -162,3 +162,63 @@ def test_near_tie_gap_conjugate_rule():
     partner = ((-(b // M)) % M) * M + (-(b % M)) % M
     assert partner != b
     assert gaps[0] > 1e-6
+
+
+# ------------------------------------------------- concealed weighting delta --
+def _conc_case(seed, H=32, W=40):
+    import synth
+    rng = np.random.default_rng(seed)
+    f, _ = synth.video_translate_edges(1, H, W, rng, n_edges=3)
+    m = synth.fixed_mask(H, W, rng)
+    cls = m.astype(np.uint8)
+    # a few projected pixels as well
+    proj = (m == 0) & (rng.random((H, W)) < 0.2)
+    cls[proj] = 2
+    return f[0].astype(np.float64), cls
+
+
+def test_concealed_delta_zero_is_plain_fsr():
+    v, cls = _conc_case(1)
+    a, _ = O.fsr_frame_concealed(v, cls, 0.0, K=30)
+    b, _ = O.fsr_frame(v, cls, K=30, track_gaps=False)
+    assert np.array_equal(a, b)
+
+
+def test_concealed_first_block_has_no_concealed_samples():
+    v, cls = _conc_case(2)
+    a, _ = O.fsr_frame_concealed(v, cls, 0.5, K=30)
+    b, _ = O.fsr_frame(v, cls, K=30, track_gaps=False)
+    assert np.array_equal(a[:4, :4], b[:4, :4])
+    assert not np.allclose(a, b)
+
+
+def test_concealed_equals_independent_block_with_explicit_concealed_class():
+    """Block (i, j) of the sequential result equals an independent FSR of
+    that block whose support marks every class-0 pixel of the raster-earlier
+    blocks as a sample of weight delta carrying its reconstructed value."""
+    from oracle.fsr import _gather, rho_table, fsr_spatial, synthesize, class_weight
+    v, cls = _conc_case(3)
+    delta = 0.4
+    out, _ = O.fsr_frame_concealed(v, cls, delta, K=25)
+    H, W = v.shape
+    for bi, bj in [(0, 3), (2, 0), (3, 5), (7, 9)]:
+        yy, xx = np.mgrid[0:H, 0:W]
+        earlier = (yy // 4 < bi) | ((yy // 4 == bi) & (xx // 4 < bj))
+        conc = earlier & (cls == 0)
+        vv = np.where(cls > 0, v, 0.0)
+        vv[conc] = out[conc]
+        aa = class_weight(cls, 1.0)
+        aa[conc] = delta
+        s, aw = _gather(vv, aa, [(bi, bj)], 4, 32)
+        c, _, _, _ = fsr_spatial(s, aw * rho_table(0.7)[None], 0.5, 25)
+        o = synthesize(c, 4)[0]
+        cb = cls[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4]
+        o[cb == 1] = v[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4][cb == 1]
+        assert np.allclose(o, out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4], atol=1e-9), (bi, bj)
+
+
+def test_concealed_given_own_output_is_identity():
+    v, cls = _conc_case(4)
+    a, ga = O.fsr_frame_concealed(v, cls, 0.5, K=20)
+    b, gb = O.fsr_frame_concealed(v, cls, 0.5, K=20, given=a)
+    assert np.array_equal(a, b) and np.array_equal(ga, gb)
