@@ -101,7 +101,18 @@ typedef struct {
     double proj_weight;  /* >= 0, weight of projected samples                 */
     int32_t precision;   /* rfsr_precision of the block DFT (0 = float64)     */
     int32_t reserved;    /* set to 0                                          */
+    double concealed_weight; /* delta, 0 <= delta <= 1 (0 = independent blocks) */
 } rfsr_fsr_params;
+
+/* Concealed weighting (the FSR setting Sec. 4 sets to 0): with delta > 0 the
+ * blocks are reconstructed in raster order and an unknown pixel of an earlier
+ * block enters the supports of later blocks as a sample of weight
+ * delta * rho^dist carrying its reconstructed (unclamped) value.  The GPU
+ * runs it as a wavefront, one launch per step t = 5 bi + bj (every
+ * raster-earlier block within a support has a smaller t; the blocks of one
+ * step never share a support), i.e. 5 (H/4 - 1) + W/4 dependent launches per
+ * frame.  Single-frame entry points only (rfsr_reconstruct_batch returns
+ * RFSR_EUNSUPPORTED for delta > 0). */
 
 /* Arithmetic of the block DFT that starts FSR (R = DFT(w s), W = DFT(w));
  * the iterations are float64 in every case.

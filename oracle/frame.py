@@ -16,7 +16,7 @@ import numpy as np
 from .me import forward_me
 from .checks import motion_check
 from .projection import project
-from .fsr import fsr_frame
+from .fsr import fsr_frame, fsr_frame_concealed
 
 
 @dataclass
@@ -36,6 +36,7 @@ class FSRParams:
     gamma: float = 0.5
     proj_weight: float = 1.0
     overwrite: str = "dfsr"
+    concealed_weight: float = 0.0     # delta; > 0: blocks in raster order (fsr_frame_concealed)
 
 
 def quantize(out):
@@ -67,8 +68,12 @@ def reconstruct_frame(cur, cur_mask, refs, me: MEParams, fsr: FSRParams, track_g
     """refs: list of (recon uint8, meas uint8, mask uint8) for lags 1..nref."""
     fields = motion_fields(cur, cur_mask, refs, me)
     values, cls = project(cur, cur_mask, fields)
-    out, gaps = fsr_frame(values, cls, fsr.block, fsr.support, fsr.rho, fsr.gamma,
-                          fsr.iters, fsr.proj_weight, fsr.overwrite, track_gaps)
+    if fsr.concealed_weight > 0:
+        out, gaps = fsr_frame_concealed(values, cls, fsr.concealed_weight, fsr.block, fsr.support,
+                                        fsr.rho, fsr.gamma, fsr.iters, fsr.proj_weight, fsr.overwrite)
+    else:
+        out, gaps = fsr_frame(values, cls, fsr.block, fsr.support, fsr.rho, fsr.gamma,
+                              fsr.iters, fsr.proj_weight, fsr.overwrite, track_gaps)
     return dict(out=out, out_u8=quantize(out), values=values, cls=cls, fields=fields,
                 gaps=gaps)
 

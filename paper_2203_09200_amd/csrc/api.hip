@@ -14,7 +14,7 @@ using namespace rfsr;
 
 namespace {
 
-constexpr int32_t kVersion = 10200;   // 1.2.0
+constexpr int32_t kVersion = 10300;   // 1.3.0
 constexpr int kMaxBatch = 4096;
 
 rfsr_status from_hip(hipError_t e) { return e == hipSuccess ? RFSR_OK : RFSR_EDEVICE; }
@@ -45,6 +45,7 @@ rfsr_status check_fsr(const rfsr_fsr_params* p) {
     if (p->overwrite != RFSR_DFSR && p->overwrite != RFSR_RFSR) return RFSR_EINVAL;
     if (p->block < 1 || p->support < p->block) return RFSR_EINVAL;
     if (p->precision < RFSR_PREC_FP64 || p->precision > RFSR_PREC_FP16X3) return RFSR_EINVAL;
+    if (!(p->concealed_weight >= 0.0 && p->concealed_weight <= 1.0)) return RFSR_EINVAL;
     if (p->block != kBlock || p->support != kSupport) return RFSR_EUNSUPPORTED;
     return RFSR_OK;
 }
@@ -482,6 +483,7 @@ rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n, con
     if (stage_events)
         for (int k = 0; k < 4; ++k)
             if (!stage_events[k]) return RFSR_EINVAL;
+    if (fsr->concealed_weight > 0.0) return RFSR_EUNSUPPORTED;
     const BatchLayout L(frames, n);
     if ((st = check_ws(workspace, ws_bytes, L.total)) != RFSR_OK) return st;
 

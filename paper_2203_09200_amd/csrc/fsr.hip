@@ -328,10 +328,16 @@ __global__ void fsr_tables_kernel(FsrTables* t, double rho) {
 // One workgroup per block of the flat block index over all the frames of
 // `js`.  (A loop over several blocks per workgroup lets the compiler hoist
 // per-lane tables out of it and spill; launches are cheap by comparison.)
-template <int PREC>
+//
+// CONC (concealed weighting delta > 0, single frame): blocks run in the
+// wavefront order t = 5 bi + bj, one launch per step, blockIdx.x counting
+// the block rows from bi0.  A support reaches 4 blocks in each direction,
+// so every raster-earlier block inside it has a smaller t (done by an
+// earlier launch) and the blocks of one step never share a support.
+template <int PREC, bool CONC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void fsr_block_kernel(
     Jobs<FrameJob> js, int total, const FsrTables* __restrict__ tab, int K, double gamma,
-    double projw, int overwrite) {
+    double projw, int overwrite, double delta, int step, int bi0) {
     // W table (32 x 32 complex double); the transpose planes reuse it.  Static,
     // so its LDS base folds into the read addresses.  The (bin, dlt) list of
     // K float4 entries is dynamic LDS.
@@ -349,9 +355,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         s_tw[2 * lane + 1] = tw[2 * lane + 1];
     }
 
-    const int gb = xcd_remap(blockIdx.x, total);
+    const int gb = CONC ? 0 : xcd_remap(blockIdx.x, total);
     {
-        const FrameJob fj = job_at(js, gb, &FrameJob::g_blk);
+        const FrameJob fj = CONC ? js.one : job_at(js, gb, &FrameJob::g_blk);
         if (fj.H == 0) return;   // empty job (stale batch table)
         const int H = fj.H, W = fj.W;
         const int64_t pitch = fj.vpitch, out_pitch = fj.pitch;
@@ -361,7 +367,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         uint8_t* __restrict__ out_u8 = fj.out_u8;
         const int nbw = W >> 2;
         const int blk = gb - fj.g_blk;
-        const int bi = blk / nbw, bj = blk - bi * nbw;
+        const int bi = CONC ? bi0 + (int)blockIdx.x : blk / nbw;
+        const int bj = CONC ? step - 5 * bi : blk - bi * nbw;
 
         // 1. gather: lane (h, c) holds support rows m = i + 16 h of column c.
         //    Loads use clamped coordinates (always in bounds); positions outside
@@ -376,14 +383,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
                 const int m = i + 16 * h;
                 const int y = y0 + m;
                 const bool in = xin && (unsigned)y < (unsigned)H;
-                const int64_t off = (int64_t)min(max(y, 0), H - 1) * pitch + xc;
+                const int yc = min(max(y, 0), H - 1);
+                const int64_t off = (int64_t)yc * pitch + xc;
                 const uint32_t k = cls[off];
                 const float v = values[off];
                 const bool known = in && (k == 1u || k == 2u);
                 const double rw = tab->rho[m * 32 + c];
                 const double a = (k == 1u) ? 1.0 : projw;
-                const double wv = known ? a * rw : 0.0;
-                const double sv = known ? (double)v : 0.0;
+                double wv = known ? a * rw : 0.0;
+                double sv = known ? (double)v : 0.0;
+                if constexpr (CONC) {
+                    // an unknown pixel of a raster-earlier block: its reconstruction, weight delta
+                    const bool conc = in && k == 0u && ((y >> 2) < bi || ((y >> 2) == bi && (x >> 2) < bj));
+                    const float cv = out[(int64_t)yc * out_pitch + xc];   // in bounds; used only if conc
+                    wv = conc ? delta * rw : wv;
+                    sv = conc ? (double)cv : sv;
+                }
                 zr[i] = wv * sv;
                 zi[i] = wv;
             }
@@ -529,12 +544,31 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
                       const FsrTables* tables, hipStream_t s) {
     if (total_blocks <= 0) return hipSuccess;
     const size_t shmem = sizeof(float4) * (size_t)p.iters;
-    auto kernel = fsr_block_kernel<RFSR_PREC_FP64>;
-    if (p.precision == RFSR_PREC_BF16X3) kernel = fsr_block_kernel<RFSR_PREC_BF16X3>;
-    else if (p.precision == RFSR_PREC_FP16X3) kernel = fsr_block_kernel<RFSR_PREC_FP16X3>;
-    hipLaunchKernelGGL(kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
-                       p.gamma, p.proj_weight, p.overwrite);
-    return hipGetLastError();
+    const bool conc = p.concealed_weight > 0.0;
+    if (conc && js.n != 0) return hipErrorInvalidValue;   // single frames only
+    auto kernel = conc ? fsr_block_kernel<RFSR_PREC_FP64, true> : fsr_block_kernel<RFSR_PREC_FP64, false>;
+    if (p.precision == RFSR_PREC_BF16X3)
+        kernel = conc ? fsr_block_kernel<RFSR_PREC_BF16X3, true> : fsr_block_kernel<RFSR_PREC_BF16X3, false>;
+    else if (p.precision == RFSR_PREC_FP16X3)
+        kernel = conc ? fsr_block_kernel<RFSR_PREC_FP16X3, true> : fsr_block_kernel<RFSR_PREC_FP16X3, false>;
+    if (!conc) {
+        hipLaunchKernelGGL(kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
+                           p.gamma, p.proj_weight, p.overwrite, 0.0, 0, 0);
+        return hipGetLastError();
+    }
+    // wavefront: step t holds the blocks with 5 bi + bj = t
+    const int nbh = js.one.H / kBlock, nbw = js.one.W / kBlock;
+    const int steps = 5 * (nbh - 1) + nbw;
+    for (int t = 0; t < steps; ++t) {
+        const int lo = t - (nbw - 1) > 0 ? (t - (nbw - 1) + 4) / 5 : 0;
+        const int hi = min(nbh - 1, t / 5);
+        if (hi < lo) continue;
+        hipLaunchKernelGGL(kernel, dim3(hi - lo + 1), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
+                           p.gamma, p.proj_weight, p.overwrite, p.concealed_weight, t, lo);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace rfsr
