@@ -27,17 +27,24 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t v, uint32_t old) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, 0xF, 0xF, false);
 }
 
+// Scalar-unit maximum of two wave-uniform values (keeps it off the vector ALU).
+__device__ __forceinline__ uint32_t smax_u32(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("s_max_u32 %0, %1, %2" : "=s"(r) : "s"(a), "s"(b));
+    return r;
+}
+
 // Maximum over the 64 lanes; the result is wave-uniform.
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     v = max(v, dpp_u32<kDppQuadXor1>(v, 0u));
     v = max(v, dpp_u32<kDppQuadXor2>(v, 0u));
     v = max(v, dpp_u32<kDppRowHalfMirror>(v, 0u));
     v = max(v, dpp_u32<kDppRowMirror>(v, 0u));
-    uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
-    uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
-    uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
-    uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)max(max(a, b), max(c, d)));
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return smax_u32(smax_u32(a, b), smax_u32(c, d));
 }
 
 // Minimum over the 64 lanes; the result is wave-uniform.

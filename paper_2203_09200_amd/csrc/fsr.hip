@@ -15,8 +15,9 @@
 //                real); R stays in registers (16 bins per lane), W goes to a
 //                32x32 LDS table
 //   4. K greedy iterations: wave argmax of |R_k|^2 (first in row-major order on
-//                ties) with DPP and permlane reductions, dlt = gamma R_b / W0,
-//                R_k -= dlt * W(k - b); the (b, dlt) list goes to LDS
+//                ties) with DPP reductions, dlt = gamma R_b / W0,
+//                R_k -= R_b * (gamma / W0) W(k - b) (the table is stored
+//                scaled); the (b, R_b) list goes to LDS
 //   5. synthesis Re sum dlt phi_b on the 16 block pixels, overwrite, store.
 //
 // Precision: everything from the gather to the energies is float64.  CDNA4
@@ -161,6 +162,29 @@ __device__ __forceinline__ double wave_allmax_f64(double v) {
     v = max_f64(v, dpp_f64<kDppRowMirror>(v));
     v = pair_max(v, 16);
     return pair_max(v, 32);
+}
+
+// Argmax over the wave of non-negative packed energies (their bit patterns
+// order like the values).  The high words are reduced first (DPP row
+// reductions, one per step, and four readlanes); only when several lanes
+// share the maximal high word (the first iterations, while the spectrum is
+// Hermitian, and near ties) are their low words reduced as well.  Returns the
+// low word of the maximum (its 5 low bits carry the row code) and, in
+// `owner`, the first lane holding it: the lanes holding one packed value all
+// own the same row, so the first is the smallest column.
+__device__ __forceinline__ uint32_t wave_argmax_packed(double v, int& owner) {
+    const uint32_t hi = (uint32_t)__double2hiint(v);
+    const uint32_t lo = (uint32_t)__double2loint(v);
+    const uint32_t mh = wave_max_u32(hi);
+    unsigned long long cand = __ballot(hi == mh);
+    if (__popcll(cand) == 1) {
+        owner = (int)__builtin_ctzll(cand);
+        return (uint32_t)__builtin_amdgcn_readlane((int)lo, owner);
+    }
+    const uint32_t ml = wave_max_u32(hi == mh ? lo : 0u);
+    cand = __ballot(hi == mh && lo == ml);
+    owner = (int)__builtin_ctzll(cand);
+    return ml;
 }
 
 // Energy with the bin's support row k1 packed into the 5 low mantissa bits
@@ -456,35 +480,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
                 __syncthreads();
             }
         }
+        // The table holds g W with g = gamma / W0, so that an update needs R_b
+        // itself: R_k -= R_b (g W_{k-b}), and the list keeps R_b (times g at
+        // synthesis).
+        const double W0 = readlane_f64(Wr[0], 0);
+        const double g = (W0 > 0.0) ? gamma / W0 : 0.0;
         double2* T = reinterpret_cast<double2*>(smem);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) T[(j + 16 * h) * 32 + c] = make_double2(Wr[j], Wi[j]);
-        const double W0 = readlane_f64(Wr[0], 0);
+        for (int j = 0; j < 16; ++j) T[(j + 16 * h) * 32 + c] = make_double2(g * Wr[j], g * Wi[j]);
         __syncthreads();
 
         // 4. greedy iterations.
-        const double g = (W0 > 0.0) ? gamma / W0 : 0.0;
         double lbe = -1.0;   // packed local maximum
 #pragma unroll
         for (int j = 0; j < 16; ++j)
             lbe = max_f64(lbe, pack_energy(fma(Rr[j], Rr[j], Ri[j] * Ri[j]), (uint32_t)(31 - 16 * h - j)));
         const uint8_t* Tb = smem;
+        const uint32_t c16 = (uint32_t)c << 4, h13 = (uint32_t)h << 13;
         for (int it = 0; it < K; ++it) {
-            const double M = wave_allmax_f64(lbe);
-            const uint32_t mlo = (uint32_t)__builtin_amdgcn_readfirstlane(
-                (int)(uint32_t)(uint64_t)__double_as_longlong(M));
+            int owner;
+            const uint32_t mlo = wave_argmax_packed(lbe, owner);
             const int b1 = 31 - (int)(mlo & 31u);
-            // lanes holding the maximum all own row b1; the first is the smallest column
-            const unsigned long long hit = __ballot(lbe == M);
-            const int owner = hit ? (int)__builtin_ctzll(hit) : (b1 >> 4) << 5;
             const int b2 = owner & 31;
             const int jb = b1 & 15;
             const double vr = Rr[jb], vi = Ri[jb];   // jb is wave-uniform: indexed register move
-            const double dr = g * readlane_f64(vr, owner);
-            const double di = g * readlane_f64(vi, owner);
+            const double dr = readlane_f64(vr, owner);   // R_b; the table carries g
+            const double di = readlane_f64(vi, owner);
             if (lane == 0)
                 list[it] = make_float4(__uint_as_float((uint32_t)(b1 * 32 + b2)), (float)dr, (float)di, 0.0f);
-            const uint32_t L = ((uint32_t)h << 13) | ((uint32_t)((c - b2) & 31) << 4);
+            const uint32_t L = ((c16 - (uint32_t)b2 * 16u) & 0x1F0u) | h13;   // per-lane column part
             lbe = -1.0;
             // issue all 16 table reads before the arithmetic so that their LDS
             // latency overlaps
@@ -522,6 +546,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         }
         gr += __shfl_xor(gr, 16);
         gr += __shfl_xor(gr, 32);
+        gr *= g;   // dlt = g R_b
         if (lane < 16) {
             const int y = 4 * bi + (p >> 2), x = 4 * bj + (p & 3);
             const int64_t off = (int64_t)y * pitch + x;

@@ -1,6 +1,7 @@
 """Small drivers to run under rocprofv3 (counter and trace collection).
 
-    python -m paper_2203_09200_amd.profiling fsr  [--reps 3]   # FSR kernel, 1080p workload frame
+    python -m paper_2203_09200_amd.profiling fsr  [--reps 3] [--delta D] [--precision P]
+                                                               # FSR kernel, 1080p workload frame
     python -m paper_2203_09200_amd.profiling copy [--mib 1024] # plain device copy of known size
 
 `fsr` launches fsr_blocks on one frame of the 1920x1080 benchmark workload
@@ -26,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
 
-def run_fsr(reps: int):
+def run_fsr(reps: int, delta: float = 0.0, precision: str = "fp64"):
     import numpy as np
     import torch
     sys.path.insert(0, ROOT)
@@ -36,10 +37,16 @@ def run_fsr(reps: int):
     meas = synth.measured(f, m)[0]
     v = torch.from_numpy(meas.astype(np.float32)).cuda()
     c = torch.from_numpy(m[0]).cuda()
-    for _ in range(reps):
-        R.fsr_blocks(v, c, R.FSRParams(iters=100))
+    prm = R.FSRParams(iters=100, concealed_weight=delta, precision=precision)
+    R.fsr_blocks(v, c, prm)
     torch.cuda.synchronize()
-    print(f"fsr_blocks x{reps} done", flush=True)
+    e0, e1 = R.Event(), R.Event()
+    e0.record()
+    for _ in range(reps):
+        R.fsr_blocks(v, c, prm)
+    e1.record()
+    print(f"fsr_blocks x{reps} done: {e0.elapsed_ms(e1) / reps:.3f} ms per 1080p frame "
+          f"(delta {delta}, precision {precision})", flush=True)
 
 
 def run_copy(mib: int):
@@ -93,6 +100,8 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     a1 = sub.add_parser("fsr")
     a1.add_argument("--reps", type=int, default=3)
+    a1.add_argument("--delta", type=float, default=0.0, help="concealed weighting")
+    a1.add_argument("--precision", default="fp64")
     a2 = sub.add_parser("copy")
     a2.add_argument("--mib", type=int, default=1024)
     a3 = sub.add_parser("record")
@@ -104,7 +113,7 @@ def main(argv=None):
     a3.add_argument("--copy-kernel", default="copyBuffer")
     a = ap.parse_args(argv)
     if a.cmd == "fsr":
-        run_fsr(a.reps)
+        run_fsr(a.reps, a.delta, a.precision)
     elif a.cmd == "copy":
         run_copy(a.mib)
     else:
