@@ -27,7 +27,7 @@ from .checks import (frmc_offsets, rmc_offsets, reverse_me, rme_accept, rmc_acce
                      median3x3, nnc_accept, motion_check, CHECKS)
 from .projection import project
 from .fsr import (rho_table, fsr_spatial, fsr_spectral, gather_supports, fsr_frame,
-                  fsr_frame_concealed)
+                  fsr_frame_concealed, fsr_pairs_spatial, fsr_pairs_spectral, fsr_pairs_blocks_out)
 from .frame import (MEParams, FSRParams, reconstruct_frame, reconstruct_sequence,
                     quantize, psnr)
 from .quality import gaussian_window, ssim, ssim_map, ssim_bruteforce
@@ -37,6 +37,7 @@ __all__ = [
     "forward_me_at", "frmc_offsets", "rmc_offsets", "reverse_me", "rme_accept",
     "rmc_accept", "median3x3", "nnc_accept", "motion_check", "CHECKS", "project",
     "rho_table", "fsr_spatial", "fsr_spectral", "gather_supports", "fsr_frame", "fsr_frame_concealed",
+    "fsr_pairs_spatial", "fsr_pairs_spectral", "fsr_pairs_blocks_out",
     "MEParams", "FSRParams", "reconstruct_frame", "reconstruct_sequence",
     "quantize", "psnr", "gaussian_window", "ssim", "ssim_map", "ssim_bruteforce",
 ]

@@ -222,3 +222,60 @@ def test_concealed_given_own_output_is_identity():
     a, ga = O.fsr_frame_concealed(v, cls, 0.5, K=20)
     b, gb = O.fsr_frame_concealed(v, cls, 0.5, K=20, given=a)
     assert np.array_equal(a, b) and np.array_equal(ga, gb)
+
+
+# ----------------------------------------------------------- conjugate pairs --
+def _uniform(M=32):
+    return np.ones((1, M, M))
+
+
+@pytest.mark.parametrize("b1,b2,phase", [(3, 5, 0.4), (0, 7, 1.1), (16, 3, -0.3), (9, 0, 2.0)])
+def test_pairs_single_cosine_closed_form(b1, b2, phase):
+    """Uniform weights make the basis orthogonal: the pair loop recovers a
+    real cosine as A (1 - (1 - gamma)^K) cos(...), picking b every time."""
+    M, A, g, K = 32, 37.0, 0.5, 7
+    m = np.arange(M)
+    s = A * np.cos(2 * np.pi * (b1 * m[:, None] + b2 * m[None, :]) / M + phase)[None]
+    c, picks = O.fsr_pairs_spatial(s, _uniform(), g, K)
+    model = (M * M * np.fft.ifft2(c[0]))
+    assert np.abs(model.imag).max() < 1e-9
+    assert np.allclose(model.real, s[0] * (1 - (1 - g) ** K), atol=1e-9)
+    first = min(b1 * M + b2, ((-b1) % M) * M + ((-b2) % M))
+    assert (picks[0] == first).all()
+
+
+def test_pairs_self_conjugate_basis():
+    M, A, g, K = 32, 20.0, 0.5, 5
+    m = np.arange(M)
+    s = (A * (-1.0) ** m[:, None] * np.ones((1, M)))[None]      # bin (16, 0)
+    c, picks = O.fsr_pairs_spatial(s, _uniform(), g, K)
+    assert (picks[0] == 16 * M).all()
+    model = (M * M * np.fft.ifft2(c[0])).real
+    assert np.allclose(model, s[0] * (1 - (1 - g) ** K), atol=1e-9)
+
+
+def test_pairs_equal_two_complex_iterations_on_orthogonal_basis():
+    """With orthogonal bases the complex loop alternates b, -b: 2K complex
+    iterations give the model of K pair iterations."""
+    M, g = 32, 0.5
+    m = np.arange(M)
+    s = (30 * np.cos(2 * np.pi * (4 * m[:, None] + 9 * m[None, :]) / M + 0.7)
+         + 12 * np.cos(2 * np.pi * (11 * m[:, None] + 2 * m[None, :]) / M - 0.2))[None]
+    cp, _ = O.fsr_pairs_spatial(s, _uniform(), g, 6)
+    cc, _, _, _ = O.fsr_spatial(s, _uniform(), g, 12)
+    assert np.allclose(cp, cc, atol=1e-9)
+
+
+def test_pairs_spatial_and_spectral_forms_agree():
+    rng = np.random.default_rng(5)
+    M = 32
+    s = rng.normal(100, 30, (6, M, M))
+    w = (rng.random((6, M, M)) < 0.4) * O.rho_table(0.7)[None]
+    ca, pa = O.fsr_pairs_spatial(s, w, 0.5, 30)
+    cb, pb = O.fsr_pairs_spectral(s, w, 0.5, 30)
+    # b and -b tie up to rounding and add the same real pair: compare modulo conjugation
+    canon = lambda p: np.minimum(p, ((-(p // M)) % M) * M + ((-(p % M)) % M))
+    assert (canon(pa) == canon(pb)).all()
+    assert np.allclose(ca, cb, atol=1e-8 * np.abs(ca).max())
+    model = np.fft.ifft2(ca, axes=(1, 2))
+    assert np.abs(model.imag).max() < 1e-9 * np.abs(model.real).max()
