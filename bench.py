@@ -34,11 +34,14 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
-def fsr_flops_per_block(K: int) -> int:
-    """Algorithmic flops of one FSR block (see DESIGN.md):
-    K iterations x 1024 bins x 11 (complex multiply-subtract 8, energy 3),
-    one 32x32 complex FFT (5 N log2 N, N = 1024), synthesis K x 16 x 4."""
-    return 11 * 1024 * K + 5 * 1024 * 10 + 64 * K
+def fsr_flops_per_block(K: int, pairs: bool = False) -> int:
+    """Algorithmic flops of one FSR block:
+    complex bins: K iterations x 1024 bins x 11 (complex multiply-subtract 8,
+    energy 3); conjugate pairs: K x 513 independent bins x 19 (two complex
+    multiply-subtracts, energy); one 32x32 complex FFT (5 N log2 N,
+    N = 1024); synthesis K x 16 x 4."""
+    it = 19 * 513 * K if pairs else 11 * 1024 * K
+    return it + 5 * 1024 * 10 + 64 * K
 
 
 def psnr(ref, test, border=40):
@@ -118,7 +121,7 @@ def run_multistream(a, dev):
     meas = [[torch.from_numpy(synth.measured(f[t], m[t])).to(dev) for t in range(T)] for f, m in data]
     masks = [[torch.from_numpy(m[t]).to(dev) for t in range(T)] for _, m in data]
     me = R.MEParams(search=a.search, check=a.check)
-    fsr = R.FSRParams(iters=a.iters, precision=a.precision)
+    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs)
     px_step = sum(h * w for h, w in sizes)
 
     ss = R.StreamSet(sizes, me, fsr, graphs=not a.no_graphs, device=dev)
@@ -201,6 +204,8 @@ def main(argv=None):
     ap.add_argument("--plain", action="store_true",
                     help="c4 only: also time the same steps one frame at a time (no batch, no graphs)")
     ap.add_argument("--no-graphs", action="store_true", help="c4 only: run batches eagerly")
+    ap.add_argument("--pairs", action="store_true",
+                    help="real-valued FSR (a conjugate pair per iteration; use about half the iterations)")
     ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3"], default="fp64",
                     help="block DFT arithmetic (float64 FFT, or matrix-core GEMMs with split "
                          "16-bit operands); the FSR iterations are float64 in every case")
@@ -236,7 +241,7 @@ def main(argv=None):
     outs = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(F)]
     outs_u8 = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(F)]
     me = R.MEParams(search=a.search, check=a.check)
-    fsr = R.FSRParams(iters=a.iters, precision=a.precision)
+    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs)
     ws = R.Workspace(dev)
     stream = torch.cuda.current_stream()
 
@@ -282,7 +287,7 @@ def main(argv=None):
     value = npx * a.steps / elapsed / 1e6
     fsr_avg_s = float(np.mean(fsr_ms)) / 1e3
     nblk = (H // 4) * (W // 4)
-    flops = fsr_flops_per_block(a.iters) * nblk
+    flops = fsr_flops_per_block(a.iters, a.pairs) * nblk
     achieved = flops / fsr_avg_s / 1e12
     traffic = traffic_from_profile(os.path.join(ROOT, "paper_2203_09200_amd", "csrc", "fsr.hip"))
     roofline = {"kernel": "fsr_block_kernel", "bound": "alu", "achieved": round(achieved, 3),
@@ -313,7 +318,8 @@ def main(argv=None):
         "config": {"workload": f"{W}x{H} uint8, {F} frames, dynamic quarter mask, D-FSR + "
                                f"{a.check.upper().replace('_', '+')}, R={a.search}, T=4, "
                                f"4x4 blocks, 32x32 support, rho=0.7, gamma=0.5, K={a.iters}, 3 references"
-                               + ("" if a.precision == "fp64" else f", block DFT {a.precision}"),
+                               + ("" if a.precision == "fp64" else f", block DFT {a.precision}")
+                               + (", conjugate-pair FSR" if a.pairs else ""),
                    "frames": F, "height": H, "width": W, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "p50_steady": round(percentile(lat_steady, 50), 3) if lat_steady else None,

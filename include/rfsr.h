@@ -100,11 +100,20 @@ typedef struct {
     double gamma;        /* 0 < gamma < 2                                     */
     double proj_weight;  /* >= 0, weight of projected samples                 */
     int32_t precision;   /* rfsr_precision of the block DFT (0 = float64)     */
-    int32_t reserved;    /* set to 0                                          */
+    int32_t pairs;       /* 0: complex single bins; 1: conjugate pairs        */
     double concealed_weight; /* delta, 0 <= delta <= 1 (0 = independent blocks) */
 } rfsr_fsr_params;
 
-/* Concealed weighting (the FSR setting Sec. 4 sets to 0): with delta > 0 the
+/* Basis selection.  pairs = 0 (default): every iteration adds one complex
+ * basis function (first maximum in row-major order), the reading used for
+ * the paper's FSR.  pairs = 1: real-valued FSR as the FSR literature uses
+ * for real images: every iteration adds the conjugate pair
+ * dlt phi_b + conj(dlt) phi_-b (one term when b = -b), so the residual stays
+ * real and only half of its spectrum is updated (R_k -= dlt W_{k-b} +
+ * conj(dlt) W_{k+b}); one pair iteration does the work of about two complex
+ * ones.  Not combined with concealed_weight > 0 (RFSR_EUNSUPPORTED).
+ *
+ * Concealed weighting (the FSR setting Sec. 4 sets to 0): with delta > 0 the
  * blocks are reconstructed in raster order and an unknown pixel of an earlier
  * block enters the supports of later blocks as a sample of weight
  * delta * rho^dist carrying its reconstructed (unclamped) value.  The GPU

@@ -137,7 +137,7 @@ def fsr_spectral(s, w, gamma, K):
     return c.reshape(nb, M, M), picks
 
 
-def fsr_pairs_spatial(s, w, gamma, K):
+def fsr_pairs_spatial(s, w, gamma, K, track_gaps=False):
     """Real-valued FSR with conjugate pairs (the form the FSR literature
     uses for real images; a variant beside the complex single-bin loop that
     is read as the paper's FSR).  Each iteration picks the first bin b in
@@ -146,7 +146,9 @@ def fsr_pairs_spatial(s, w, gamma, K):
     is the one with b1 <= 16), dlt = gamma R_b / W0, and adds the real pair
     dlt phi_b + conj(dlt) phi_-b to the model (dlt phi_b alone, real, when
     b = -b); the residual stays real.  Returns (c (nb,M,M) complex,
-    picks (nb,K))."""
+    picks (nb,K)) and, with track_gaps, gaps (nb,): the minimum over
+    iterations of (E_best - E_next) / E_best with the chosen bin and its
+    conjugate partner excluded from E_next."""
     s = np.asarray(s, np.float64)
     w = np.asarray(w, np.float64)
     nb, M, _ = w.shape
@@ -156,6 +158,7 @@ def fsr_pairs_spatial(s, w, gamma, K):
     W0 = w.sum(axis=(1, 2))
     safe = W0 > 0
     picks = np.zeros((nb, K), np.int64)
+    gaps = np.full(nb, np.inf)
     for it in range(K):
         Rs = np.fft.fft2(w * r).reshape(nb, M * M)
         E = Rs.real ** 2 + Rs.imag ** 2
@@ -165,12 +168,21 @@ def fsr_pairs_spatial(s, w, gamma, K):
         b1, b2 = b // M, b % M
         partner = ((-b1) % M) * M + ((-b2) % M)
         self_conj = partner == b
+        if track_gaps:
+            E1 = E[idx, b]
+            Es = E.copy()
+            Es[idx, b] = -np.inf
+            Es[idx, partner] = -np.inf
+            with np.errstate(divide="ignore", invalid="ignore"):
+                gaps = np.minimum(gaps, np.where(E1 > 0, (E1 - Es.max(axis=1)) / E1, np.inf))
         c[idx, b] += dlt
         c[idx[~self_conj], partner[~self_conj]] += np.conj(dlt[~self_conj])
         phi = _basis(b1, b2, M)
         # real update: dlt phi_b (+ its conjugate for a pair)
         upd = dlt[:, None, None] * phi
         r -= np.where(self_conj[:, None, None], upd.real, 2.0 * upd.real)
+    if track_gaps:
+        return c.reshape(nb, M, M), picks, gaps
     return c.reshape(nb, M, M), picks
 
 
@@ -213,14 +225,15 @@ def fsr_pairs_spectral(s, w, gamma, K):
 def fsr_pairs_blocks_out(values, cls, blocks, B=4, M=32, rho=0.7, gamma=0.5, K=50,
                          proj_weight=1.0, overwrite="dfsr", chunk=2048):
     """Conjugate-pair FSR of the listed blocks (overwrite as fsr_blocks_out).
-    Returns out (nb, B, B) float64."""
+    Returns (out (nb, B, B) float64, gaps (nb,))."""
     blocks = np.asarray(blocks, np.int64).reshape(-1, 2)
     tab = rho_table(rho, M)
-    outs = []
+    outs, gaps = [], []
     for i in range(0, blocks.shape[0], chunk):
         blk = blocks[i:i + chunk]
         s, a = gather_supports(values, cls, blk, B, M, proj_weight)
-        c, _ = fsr_pairs_spatial(s, a * tab[None], gamma, K)
+        c, _, g = fsr_pairs_spatial(s, a * tab[None], gamma, K, track_gaps=True)
+        gaps.append(g)
         out = synthesize(c, B)
         for j, (bi, bj) in enumerate(blk):
             cb = cls[B * bi:B * bi + B, B * bj:B * bj + B]
@@ -228,7 +241,7 @@ def fsr_pairs_blocks_out(values, cls, blocks, B=4, M=32, rho=0.7, gamma=0.5, K=5
             keep = (cb == 1) if overwrite == "dfsr" else (cb >= 1)
             out[j][keep] = vb[keep]
         outs.append(out)
-    return np.concatenate(outs)
+    return np.concatenate(outs), np.concatenate(gaps)
 
 
 def synthesize(c, B):

@@ -37,7 +37,7 @@ class _FSRParams(ctypes.Structure):
                 ("iters", ctypes.c_int32), ("overwrite", ctypes.c_int32),
                 ("rho", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("proj_weight", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("concealed_weight", ctypes.c_double)]
+                ("pairs", ctypes.c_int32), ("concealed_weight", ctypes.c_double)]
 
 
 @dataclass
@@ -64,11 +64,12 @@ class FSRParams:
     support: int = 32
     precision: str = "fp64"     # block DFT: "fp64", "bf16x3" or "fp16x3" (matrix cores)
     concealed_weight: float = 0.0   # delta > 0: raster-order blocks (wavefront), single frames only
+    pairs: bool = False             # real-valued FSR: conjugate pairs per iteration
 
     def c(self) -> _FSRParams:
         return _FSRParams(self.block, self.support, self.iters, OVERWRITE[self.overwrite],
-                          self.rho, self.gamma, self.proj_weight, PRECISION[self.precision], 0,
-                          self.concealed_weight)
+                          self.rho, self.gamma, self.proj_weight, PRECISION[self.precision],
+                          int(self.pairs), self.concealed_weight)
 
 
 class FrameDesc(ctypes.Structure):

@@ -14,7 +14,7 @@ using namespace rfsr;
 
 namespace {
 
-constexpr int32_t kVersion = 10300;   // 1.3.0
+constexpr int32_t kVersion = 10400;   // 1.4.0
 constexpr int kMaxBatch = 4096;
 
 rfsr_status from_hip(hipError_t e) { return e == hipSuccess ? RFSR_OK : RFSR_EDEVICE; }
@@ -46,6 +46,8 @@ rfsr_status check_fsr(const rfsr_fsr_params* p) {
     if (p->block < 1 || p->support < p->block) return RFSR_EINVAL;
     if (p->precision < RFSR_PREC_FP64 || p->precision > RFSR_PREC_FP16X3) return RFSR_EINVAL;
     if (!(p->concealed_weight >= 0.0 && p->concealed_weight <= 1.0)) return RFSR_EINVAL;
+    if (p->pairs != 0 && p->pairs != 1) return RFSR_EINVAL;
+    if (p->pairs && p->concealed_weight > 0.0) return RFSR_EUNSUPPORTED;
     if (p->block != kBlock || p->support != kSupport) return RFSR_EUNSUPPORTED;
     return RFSR_OK;
 }

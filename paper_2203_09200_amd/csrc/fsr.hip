@@ -358,7 +358,13 @@ __global__ void fsr_tables_kernel(FsrTables* t, double rho) {
 // the block rows from bi0.  A support reaches 4 blocks in each direction,
 // so every raster-earlier block inside it has a smaller t (done by an
 // earlier launch) and the blocks of one step never share a support.
-template <int PREC, bool CONC>
+//
+// PAIRS (real-valued FSR): each iteration adds the conjugate pair dlt phi_b +
+// conj(dlt) phi_-b, so the residual stays real and its spectrum Hermitian.
+// The loop keeps only registers j = 0..8 of the layout (rows 0..8 and
+// 16..24, which contain every row 0..16 or its conjugate), updates
+// R_k -= dlt W(k - b) + conj(dlt) W(k + b) and halves dlt when b = -b.
+template <int PREC, bool CONC, bool PAIRS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void fsr_block_kernel(
     Jobs<FrameJob> js, int total, const FsrTables* __restrict__ tab, int K, double gamma,
     double projw, int overwrite, double delta, int step, int bi0) {
@@ -491,9 +497,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         __syncthreads();
 
         // 4. greedy iterations.
+        constexpr int NJ = PAIRS ? 9 : 16;   // registers in the loop
         double lbe = -1.0;   // packed local maximum
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
+        for (int j = 0; j < NJ; ++j)
             lbe = max_f64(lbe, pack_energy(fma(Rr[j], Rr[j], Ri[j] * Ri[j]), (uint32_t)(31 - 16 * h - j)));
         const uint8_t* Tb = smem;
         const uint32_t c16 = (uint32_t)c << 4, h13 = (uint32_t)h << 13;
@@ -504,30 +511,58 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             const int b2 = owner & 31;
             const int jb = b1 & 15;
             const double vr = Rr[jb], vi = Ri[jb];   // jb is wave-uniform: indexed register move
-            const double dr = readlane_f64(vr, owner);   // R_b; the table carries g
-            const double di = readlane_f64(vi, owner);
+            double dr = readlane_f64(vr, owner);   // R_b; the table carries g
+            double di = readlane_f64(vi, owner);
+            if (PAIRS && (b1 & 15) == 0 && (b2 & 15) == 0) {   // b = -b: one real term
+                dr *= 0.5;
+                di *= 0.5;
+            }
             if (lane == 0)
                 list[it] = make_float4(__uint_as_float((uint32_t)(b1 * 32 + b2)), (float)dr, (float)di, 0.0f);
             const uint32_t L = ((c16 - (uint32_t)b2 * 16u) & 0x1F0u) | h13;   // per-lane column part
             lbe = -1.0;
-            // issue all 16 table reads before the arithmetic so that their LDS
-            // latency overlaps
-            double2 wt[16];
+            if constexpr (!PAIRS) {
+                // issue all 16 table reads before the arithmetic so that their
+                // LDS latency overlaps
+                double2 wt[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const uint32_t S = (uint32_t)((j - b1) & 31) << 9;   // wave-uniform row part
-                wt[j] = *reinterpret_cast<const double2*>(Tb + (S ^ L));
-            }
+                for (int j = 0; j < 16; ++j) {
+                    const uint32_t S = (uint32_t)((j - b1) & 31) << 9;   // wave-uniform row part
+                    wt[j] = *reinterpret_cast<const double2*>(Tb + (S ^ L));
+                }
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const double2 wv = wt[j];
-                double xr = fma(-dr, wv.x, Rr[j]);
-                xr = fma(di, wv.y, xr);
-                double xi = fma(-dr, wv.y, Ri[j]);
-                xi = fma(-di, wv.x, xi);
-                Rr[j] = xr;
-                Ri[j] = xi;
-                lbe = max_f64(lbe, pack_energy(fma(xr, xr, xi * xi), (uint32_t)(31 - 16 * h - j)));
+                for (int j = 0; j < 16; ++j) {
+                    const double2 wv = wt[j];
+                    double xr = fma(-dr, wv.x, Rr[j]);
+                    xr = fma(di, wv.y, xr);
+                    double xi = fma(-dr, wv.y, Ri[j]);
+                    xi = fma(-di, wv.x, xi);
+                    Rr[j] = xr;
+                    Ri[j] = xi;
+                    lbe = max_f64(lbe, pack_energy(fma(xr, xr, xi * xi), (uint32_t)(31 - 16 * h - j)));
+                }
+            } else {
+                const uint32_t Lp = ((c16 + (uint32_t)b2 * 16u) & 0x1F0u) | h13;
+                double2 wm[NJ], wp[NJ];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    wm[j] = *reinterpret_cast<const double2*>(Tb + (((uint32_t)((j - b1) & 31) << 9) ^ L));
+                    wp[j] = *reinterpret_cast<const double2*>(Tb + (((uint32_t)((j + b1) & 31) << 9) ^ Lp));
+                }
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    double xr = fma(-dr, wm[j].x, Rr[j]);
+                    xr = fma(-dr, wp[j].x, xr);
+                    xr = fma(di, wm[j].y, xr);
+                    xr = fma(-di, wp[j].y, xr);
+                    double xi = fma(-dr, wm[j].y, Ri[j]);
+                    xi = fma(-dr, wp[j].y, xi);
+                    xi = fma(-di, wm[j].x, xi);
+                    xi = fma(di, wp[j].x, xi);
+                    Rr[j] = xr;
+                    Ri[j] = xi;
+                    lbe = max_f64(lbe, pack_energy(fma(xr, xr, xi * xi), (uint32_t)(31 - 16 * h - j)));
+                }
             }
         }
         __syncthreads();
@@ -546,7 +581,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         }
         gr += __shfl_xor(gr, 16);
         gr += __shfl_xor(gr, 32);
-        gr *= g;   // dlt = g R_b
+        gr *= PAIRS ? 2.0 * g : g;   // dlt = g R_b; a pair adds 2 Re(dlt phi_b)
         if (lane < 16) {
             const int y = 4 * bi + (p >> 2), x = 4 * bj + (p & 3);
             const int64_t off = (int64_t)y * pitch + x;
@@ -571,11 +606,20 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
     const size_t shmem = sizeof(float4) * (size_t)p.iters;
     const bool conc = p.concealed_weight > 0.0;
     if (conc && js.n != 0) return hipErrorInvalidValue;   // single frames only
-    auto kernel = conc ? fsr_block_kernel<RFSR_PREC_FP64, true> : fsr_block_kernel<RFSR_PREC_FP64, false>;
-    if (p.precision == RFSR_PREC_BF16X3)
-        kernel = conc ? fsr_block_kernel<RFSR_PREC_BF16X3, true> : fsr_block_kernel<RFSR_PREC_BF16X3, false>;
-    else if (p.precision == RFSR_PREC_FP16X3)
-        kernel = conc ? fsr_block_kernel<RFSR_PREC_FP16X3, true> : fsr_block_kernel<RFSR_PREC_FP16X3, false>;
+    if (conc && p.pairs) return hipErrorInvalidValue;     // not combined
+    auto kernel = fsr_block_kernel<RFSR_PREC_FP64, false, false>;
+    if (p.pairs) {
+        kernel = fsr_block_kernel<RFSR_PREC_FP64, false, true>;
+        if (p.precision == RFSR_PREC_BF16X3) kernel = fsr_block_kernel<RFSR_PREC_BF16X3, false, true>;
+        else if (p.precision == RFSR_PREC_FP16X3) kernel = fsr_block_kernel<RFSR_PREC_FP16X3, false, true>;
+    } else if (conc) {
+        kernel = fsr_block_kernel<RFSR_PREC_FP64, true, false>;
+        if (p.precision == RFSR_PREC_BF16X3) kernel = fsr_block_kernel<RFSR_PREC_BF16X3, true, false>;
+        else if (p.precision == RFSR_PREC_FP16X3) kernel = fsr_block_kernel<RFSR_PREC_FP16X3, true, false>;
+    } else {
+        if (p.precision == RFSR_PREC_BF16X3) kernel = fsr_block_kernel<RFSR_PREC_BF16X3, false, false>;
+        else if (p.precision == RFSR_PREC_FP16X3) kernel = fsr_block_kernel<RFSR_PREC_FP16X3, false, false>;
+    }
     if (!conc) {
         hipLaunchKernelGGL(kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
                            p.gamma, p.proj_weight, p.overwrite, 0.0, 0, 0);

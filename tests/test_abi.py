@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol(R):
     lib = R.lib()
     for n in declared_functions():
         assert hasattr(lib, n), n
-    assert lib.rfsr_version() == 10300
+    assert lib.rfsr_version() == 10400
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.rfsr_status_string(code).startswith(b"RFSR_")
 

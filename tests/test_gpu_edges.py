@@ -30,8 +30,10 @@ def test_fsr_extreme_shapes_sampled(H, W):
     got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
     d = np.abs(got - ora).max(axis=(1, 2))
     amb = gaps < TAU_FP32
-    print(f"{H}x{W}: max {d[~amb].max():.2e} over {(~amb).sum()} blocks")
-    assert d[~amb].max() <= FSR_TOL
+    assert np.isfinite(out).all()
+    if (~amb).any():      # a frame of one block may hold only a near tie
+        print(f"{H}x{W}: max {d[~amb].max():.2e} over {(~amb).sum()} blocks")
+        assert d[~amb].max() <= FSR_TOL
 
 
 @pytest.mark.parametrize("H,W", [(16, 16384), (16384, 16)])
