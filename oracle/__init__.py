@@ -23,7 +23,7 @@ Readings of points the paper leaves open are listed in each module header.
 """
 from .me import (template_offsets, cost_at, reverse_cost_at, n_map, forward_me,
                  forward_me_at)
-from .checks import (frmc_offsets, rmc_offsets, reverse_me, rme_accept, rmc_accept,
+from .checks import (frmc_offsets, rmc_offsets, reverse_me, rme_accept, rmc_accept, rmc_accept_at,
                      median3x3, nnc_accept, motion_check, CHECKS)
 from .projection import project
 from .fsr import (rho_table, fsr_spatial, fsr_spectral, gather_supports, fsr_frame,
@@ -35,7 +35,7 @@ from .quality import gaussian_window, ssim, ssim_map, ssim_bruteforce
 __all__ = [
     "template_offsets", "cost_at", "reverse_cost_at", "n_map", "forward_me",
     "forward_me_at", "frmc_offsets", "rmc_offsets", "reverse_me", "rme_accept",
-    "rmc_accept", "median3x3", "nnc_accept", "motion_check", "CHECKS", "project",
+    "rmc_accept", "rmc_accept_at", "median3x3", "nnc_accept", "motion_check", "CHECKS", "project",
     "rho_table", "fsr_spatial", "fsr_spectral", "gather_supports", "fsr_frame", "fsr_frame_concealed",
     "fsr_pairs_spatial", "fsr_pairs_spectral", "fsr_pairs_blocks_out",
     "MEParams", "FSRParams", "reconstruct_frame", "reconstruct_sequence",

@@ -120,6 +120,26 @@ def rmc_accept(cur, mask, ref, alpha, beta, offsets, T=4, where=None):
     return acc, evals
 
 
+def rmc_accept_at(cur, mask, ref, ys, xs, alpha, beta, offsets, T=4):
+    """`rmc_accept` at selected pixels only: alpha, beta are the vectors at
+    (ys, xs).  Returns bool array of the same shape as ys."""
+    H, W = cur.shape
+    ys, xs = np.asarray(ys, np.int64), np.asarray(xs, np.int64)
+    alpha, beta = np.asarray(alpha, np.int64), np.asarray(beta, np.int64)
+    Sg, ng = cost_at(cur, mask, ref, ys, xs, alpha, beta, T)
+    acc = np.ones(ys.shape, bool)
+    for dy in offsets:
+        for dx in offsets:
+            if dy == 0 and dx == 0:
+                continue
+            sy, sx = ys + dy, xs + dx
+            ins = _inside(sy, sx, H, W)
+            Sr, nr = cost_at(cur, mask, ref, np.clip(sy, 0, H - 1), np.clip(sx, 0, W - 1),
+                             alpha - dy, beta - dx, T)
+            acc &= ~(ins & (Sr * ng <= Sg * nr))
+    return acc
+
+
 def median3x3(a):
     """Component-wise 3x3 median, edge-replicated borders (Eq. (1))."""
     a = np.asarray(a)

@@ -207,3 +207,18 @@ def test_cascade_is_conjunction():
     cas, ev_cas = O.motion_check("nnc_frmc", cur, mask, frames[0], a, b, 6)
     assert (cas == (nn & fr)).all()
     assert ev_cas <= ev_full
+
+
+def test_rmc_accept_at_equals_full_frame():
+    import synth
+    rng = np.random.default_rng(12)
+    H, W = 24, 28
+    frames, _ = synth.video_translate_edges(2, H, W, rng, max_step=2, n_edges=3)
+    m = synth.fixed_mask(H, W, rng)
+    cur = frames[1] * m
+    a, b, S, n = O.forward_me(cur, m, frames[0], 4)
+    for offs in (O.frmc_offsets(), O.rmc_offsets(3)):
+        full, _ = O.rmc_accept(cur, m, frames[0], a, b, offs)
+        ys, xs = np.mgrid[0:H, 0:W]
+        at = O.rmc_accept_at(cur, m, frames[0], ys.ravel(), xs.ravel(), a.ravel(), b.ravel(), offs)
+        assert np.array_equal(at.reshape(H, W), full)
