@@ -54,7 +54,7 @@ def _basis(b1, b2, M):
     return e1[:, :, None] * e2[:, None, :]
 
 
-def fsr_spatial(s, w, gamma, K, track_gaps=False, stop_ratio=0.0):
+def fsr_spatial(s, w, gamma, K, track_gaps=False):
     """Greedy FSR on a batch of supports (independent blocks).
 
     s: (nb, M, M) real or complex samples (0 where unknown), w: (nb, M, M)
@@ -62,11 +62,6 @@ def fsr_spatial(s, w, gamma, K, track_gaps=False, stop_ratio=0.0):
     picks (nb,K) flat bin indices, gaps (nb,) or None, (energies, chosen)):
     energies[i] = sum w |r|^2 after iteration i, chosen[i] = |R_b|^2 of the
     bin chosen at iteration i.
-
-    stop_ratio > 0 (residual-energy early stop, an FSR-literature option the
-    paper's configuration does not use): a block stops before iteration
-    i >= 1 once |R_b|^2 of the bin it would choose is below stop_ratio times
-    that of iteration 0; stopped blocks pick -1 and change nothing.
 
     With track_gaps, gaps[b] is the minimum over iterations of
     (E_best - E_next) / E_best, where E_next excludes the chosen bin and,
@@ -87,27 +82,14 @@ def fsr_spatial(s, w, gamma, K, track_gaps=False, stop_ratio=0.0):
     herm = np.full(nb, bool(np.isrealobj(s) or not np.any(np.imag(s))))
     energies = []      # weighted residual energy sum w|r|^2 after each iteration
     chosen = []        # |R_b|^2 of the chosen bin at each iteration
-    active = np.ones(nb, bool)
-    E0 = None
     for it in range(K):
         Rs = np.fft.fft2(w * r).reshape(nb, M * M)
         E = Rs.real ** 2 + Rs.imag ** 2
         b = E.argmax(axis=1)
+        picks[:, it] = b
         Rb = Rs[idx, b]
-        if stop_ratio > 0:
-            Eb = E[idx, b]
-            if it == 0:
-                E0 = Eb.copy()
-            else:
-                thr = stop_ratio * E0
-                if track_gaps:   # a decision within rounding of the threshold is a near tie too
-                    with np.errstate(divide="ignore", invalid="ignore"):
-                        tg = np.where(active & (Eb > 0), np.abs(Eb - thr) / Eb, np.inf)
-                    gaps = np.minimum(gaps, tg)
-                active &= Eb >= thr
-        picks[:, it] = np.where(active, b, -1)
-        chosen.append(np.where(active, E[idx, b], 0.0))
-        dlt = np.where(safe & active, gamma * Rb / np.where(safe, W0, 1.0), 0.0)
+        chosen.append(E[idx, b])
+        dlt = np.where(safe, gamma * Rb / np.where(safe, W0, 1.0), 0.0)
         c[idx, b] += dlt
         b1, b2 = b // M, b % M
         r -= dlt[:, None, None] * _basis(b1, b2, M)
@@ -120,7 +102,7 @@ def fsr_spatial(s, w, gamma, K, track_gaps=False, stop_ratio=0.0):
             Es[idx[hp], partner[hp]] = -np.inf
             E2 = Es.max(axis=1)
             with np.errstate(divide="ignore", invalid="ignore"):
-                g = np.where(active & (E1 > 0), (E1 - E2) / E1, np.inf)
+                g = np.where(E1 > 0, (E1 - E2) / E1, np.inf)
             gaps = np.minimum(gaps, g)
             herm &= partner == b
         energies.append((w * np.abs(r) ** 2).sum(axis=(1, 2)))
@@ -299,7 +281,7 @@ def gather_supports(values, cls, blocks, B=4, M=32, proj_weight=1.0):
 
 
 def fsr_blocks_out(values, cls, blocks, B=4, M=32, rho=0.7, gamma=0.5, K=100,
-                   proj_weight=1.0, overwrite="dfsr", track_gaps=True, chunk=2048, stop_ratio=0.0):
+                   proj_weight=1.0, overwrite="dfsr", track_gaps=True, chunk=2048):
     """FSR of the listed blocks.  Returns (out (nb,B,B) float64, gaps (nb,))."""
     blocks = np.asarray(blocks, np.int64).reshape(-1, 2)
     tab = rho_table(rho, M)
@@ -307,7 +289,7 @@ def fsr_blocks_out(values, cls, blocks, B=4, M=32, rho=0.7, gamma=0.5, K=100,
     for i in range(0, blocks.shape[0], chunk):
         blk = blocks[i:i + chunk]
         s, a = gather_supports(values, cls, blk, B, M, proj_weight)
-        c, _, g, _ = fsr_spatial(s, a * tab[None], gamma, K, track_gaps=track_gaps, stop_ratio=stop_ratio)
+        c, _, g, _ = fsr_spatial(s, a * tab[None], gamma, K, track_gaps=track_gaps)
         out = synthesize(c, B)
         # overwrite with measured (D-FSR) or measured + projected (R-FSR) values
         for j, (bi, bj) in enumerate(blk):
@@ -379,11 +361,11 @@ def all_blocks(H, W, B=4):
 
 
 def fsr_frame(values, cls, B=4, M=32, rho=0.7, gamma=0.5, K=100, proj_weight=1.0,
-              overwrite="dfsr", track_gaps=True, stop_ratio=0.0):
+              overwrite="dfsr", track_gaps=True):
     """FSR of a whole frame.  Returns (out (H,W) float64, gaps (H/B, W/B))."""
     H, W = values.shape
     blocks = all_blocks(H, W, B)
     out_b, gaps = fsr_blocks_out(values, cls, blocks, B, M, rho, gamma, K, proj_weight,
-                                 overwrite, track_gaps, stop_ratio=stop_ratio)
+                                 overwrite, track_gaps)
     out = out_b.reshape(H // B, W // B, B, B).transpose(0, 2, 1, 3).reshape(H, W)
     return out, gaps.reshape(H // B, W // B)

@@ -279,40 +279,3 @@ def test_pairs_spatial_and_spectral_forms_agree():
     assert np.allclose(ca, cb, atol=1e-8 * np.abs(ca).max())
     model = np.fft.ifft2(ca, axes=(1, 2))
     assert np.abs(model.imag).max() < 1e-9 * np.abs(model.real).max()
-
-
-# ------------------------------------------------------------- early stop --
-def test_early_stop_zero_ratio_is_plain_loop():
-    rng = np.random.default_rng(8)
-    s = rng.normal(100, 30, (5, 32, 32))
-    w = (rng.random((5, 32, 32)) < 0.3) * O.rho_table(0.7)[None]
-    a = O.fsr_spatial(s, w, 0.5, 40)
-    b = O.fsr_spatial(s, w, 0.5, 40, stop_ratio=0.0)
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-
-
-def test_early_stop_single_basis_iteration_count():
-    """Uniform weights, one complex basis function: the chosen energy after i
-    iterations is (1-gamma)^(2i) E0, so with ratio r the loop stops before
-    the first i with (1-gamma)^(2i) < r."""
-    M, g = 32, 0.5
-    m = np.arange(M)
-    s = 50 * np.exp(2j * np.pi * (3 * m[:, None] + 5 * m[None, :]) / M)[None]
-    for r, n in ((0.5, 1), (0.2, 2), (0.01, 4), (1e-4, 7)):
-        c, picks, _, _ = O.fsr_spatial(s, np.ones((1, M, M)), g, 20, stop_ratio=r)
-        done = int((picks[0] >= 0).sum())
-        assert done == n, (r, done)
-        assert (picks[0, done:] == -1).all()
-        assert np.isclose(np.abs(c[0, 3, 5]), 50 * (1 - (1 - g) ** n))
-
-
-def test_early_stop_prefix_of_full_loop():
-    rng = np.random.default_rng(9)
-    s = rng.normal(100, 30, (6, 32, 32))
-    w = (rng.random((6, 32, 32)) < 0.3) * O.rho_table(0.7)[None]
-    full = O.fsr_spatial(s, w, 0.5, 60)[1]
-    stop = O.fsr_spatial(s, w, 0.5, 60, stop_ratio=1e-3)[1]
-    for i in range(6):
-        n = int((stop[i] >= 0).sum())
-        assert 1 <= n <= 60
-        assert np.array_equal(stop[i, :n], full[i, :n])
