@@ -121,7 +121,7 @@ def run_multistream(a, dev):
     meas = [[torch.from_numpy(synth.measured(f[t], m[t])).to(dev) for t in range(T)] for f, m in data]
     masks = [[torch.from_numpy(m[t]).to(dev) for t in range(T)] for _, m in data]
     me = R.MEParams(search=a.search, check=a.check)
-    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs)
+    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs, concealed_weight=a.concealed)
     px_step = sum(h * w for h, w in sizes)
 
     ss = R.StreamSet(sizes, me, fsr, graphs=not a.no_graphs, device=dev)
@@ -176,7 +176,8 @@ def run_multistream(a, dev):
         "config": {"workload": f"48 streams (16x352x288, 16x1280x720, 12x1920x1080, 4x3840x2160), "
                                f"{T} frames cycled, even streams fixed mask / odd dynamic, D-FSR + "
                                f"{a.check.upper().replace('_', '+')}, R={a.search}, K={a.iters}, 3 references, "
-                               f"one batch per time step" + ("" if a.no_graphs else ", graph replay"),
+                               f"one batch per time step" + ("" if a.no_graphs else ", graph replay")
+                               + (f", concealed weighting {a.concealed}" if a.concealed else ""),
                    "streams": len(sizes), "hr_px_per_step": px_step, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
         "psnr_db": round(q, 3),
@@ -204,6 +205,8 @@ def main(argv=None):
     ap.add_argument("--plain", action="store_true",
                     help="c4 only: also time the same steps one frame at a time (no batch, no graphs)")
     ap.add_argument("--no-graphs", action="store_true", help="c4 only: run batches eagerly")
+    ap.add_argument("--concealed", type=float, default=0.0,
+                    help="concealed weighting delta (> 0: raster-order blocks as a wavefront)")
     ap.add_argument("--pairs", action="store_true",
                     help="real-valued FSR (a conjugate pair per iteration; use about half the iterations)")
     ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3"], default="fp64",
@@ -241,7 +244,7 @@ def main(argv=None):
     outs = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(F)]
     outs_u8 = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(F)]
     me = R.MEParams(search=a.search, check=a.check)
-    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs)
+    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs, concealed_weight=a.concealed)
     ws = R.Workspace(dev)
     stream = torch.cuda.current_stream()
 
@@ -319,7 +322,8 @@ def main(argv=None):
                                f"{a.check.upper().replace('_', '+')}, R={a.search}, T=4, "
                                f"4x4 blocks, 32x32 support, rho=0.7, gamma=0.5, K={a.iters}, 3 references"
                                + ("" if a.precision == "fp64" else f", block DFT {a.precision}")
-                               + (", conjugate-pair FSR" if a.pairs else ""),
+                               + (", conjugate-pair FSR" if a.pairs else "")
+                               + (f", concealed weighting {a.concealed}" if a.concealed else ""),
                    "frames": F, "height": H, "width": W, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "p50_steady": round(percentile(lat_steady, 50), 3) if lat_steady else None,

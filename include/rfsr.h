@@ -120,8 +120,9 @@ typedef struct {
  * runs it as a wavefront, one launch per step t = 5 bi + bj (every
  * raster-earlier block within a support has a smaller t; the blocks of one
  * step never share a support), i.e. 5 (H/4 - 1) + W/4 dependent launches per
- * frame.  Single-frame entry points only (rfsr_reconstruct_batch returns
- * RFSR_EUNSUPPORTED for delta > 0). */
+ * frame.  rfsr_reconstruct_batch runs the steps of all its frames together
+ * (one launch per step holding every frame's blocks of that step), so many
+ * streams fill the GPU that one frame's wavefront leaves idle. */
 
 /* Arithmetic of the block DFT that starts FSR (R = DFT(w s), W = DFT(w));
  * the iterations are float64 in every case.

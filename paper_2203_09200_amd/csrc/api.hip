@@ -485,7 +485,6 @@ rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n, con
     if (stage_events)
         for (int k = 0; k < 4; ++k)
             if (!stage_events[k]) return RFSR_EINVAL;
-    if (fsr->concealed_weight > 0.0) return RFSR_EUNSUPPORTED;
     const BatchLayout L(frames, n);
     if ((st = check_ws(workspace, ws_bytes, L.total)) != RFSR_OK) return st;
 
@@ -510,7 +509,7 @@ rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n, con
     record(1);
     if (e == hipSuccess) e = launch_project(jf, p.px_frames, s);
     record(2);
-    if (e == hipSuccess) e = launch_fsr(jf, p.blocks, *fsr, tab, s);
+    if (e == hipSuccess) e = launch_fsr(jf, p.blocks, *fsr, tab, s, p.frames.data());
     record(3);
     return from_hip(e);
 }

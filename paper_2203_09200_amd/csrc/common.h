@@ -186,6 +186,16 @@ __device__ __forceinline__ J job_at(const Jobs<J>& js, int g, int J::*base) {
     return t[lo];
 }
 
+// Concealed-weighting wavefront: step t holds the blocks with 5 bi + bj = t,
+// i.e. block rows [lo, hi] (empty when hi < lo); an H x W frame has
+// wave_steps(H, W) steps.
+__host__ __device__ inline void wave_rows(int H, int W, int t, int& lo, int& hi) {
+    const int nbh = H / 4, nbw = W / 4;
+    lo = t - (nbw - 1) > 0 ? (t - (nbw - 1) + 4) / 5 : 0;
+    hi = nbh - 1 < t / 5 ? nbh - 1 : t / 5;
+}
+__host__ __device__ inline int wave_steps(int H, int W) { return 5 * (H / 4 - 1) + W / 4; }
+
 constexpr int kPad = 16;         // border of the window planes
 constexpr int kMeTile = 16;      // forward ME tile edge
 constexpr int kFrmcRun = 2048;   // pixels per FRMC workgroup (cascade)
@@ -200,9 +210,11 @@ __host__ __device__ inline int frmc_groups(int H, int W) { return (H * W + kFrmc
 // --------------------------------------------------------------- launches --
 // Each returns hipSuccess or the launch error.
 hipError_t launch_fsr_tables(FsrTables* t, double rho, hipStream_t s);
-// FSR over all `total_blocks` blocks of the frames in `js`.
+// FSR over all `total_blocks` blocks of the frames in `js`.  With a
+// concealed weighting and a job table, `host_frames` is the host copy of the
+// table (frame sizes for the wavefront grid).
 hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
-                      const FsrTables* tables, hipStream_t s);
+                      const FsrTables* tables, hipStream_t s, const FrameJob* host_frames = nullptr);
 
 // Window planes of the frames in `js` (frames with fm == nullptr skipped).
 hipError_t launch_windows(const Jobs<FrameJob>& js, int total_groups, hipStream_t s);

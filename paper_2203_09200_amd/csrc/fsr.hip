@@ -199,6 +199,28 @@ __device__ __forceinline__ double pack_energy(double e, uint32_t code) {
 
 constexpr int kPlane = 33;                       // padded row length of a transpose plane
 
+// Frame and block row of this workgroup on wavefront step `step`: a single
+// frame counts rows from bi0; a batch counts the step's blocks frame after
+// frame in table order.
+__device__ __forceinline__ FrameJob wave_job(const Jobs<FrameJob>& js, int step, int bi0, int& bi) {
+    bi = bi0 + (int)blockIdx.x;
+    if (js.n == 0) return js.one;
+    if (*(const_ptr<unsigned long long>)(uintptr_t)js.stamp != js.key) return js.one;   // empty job
+    const_ptr<FrameJob> t = (const_ptr<FrameJob>)(uintptr_t)js.table;
+    int g = (int)blockIdx.x;
+    for (int f = 0; f < js.n; ++f) {
+        int lo, hi;
+        wave_rows(t[f].H, t[f].W, step, lo, hi);
+        const int cnt = hi >= lo ? hi - lo + 1 : 0;
+        if (g < cnt) {
+            bi = lo + g;
+            return t[f];
+        }
+        g -= cnt;
+    }
+    return js.one;   // beyond the step's blocks: empty job
+}
+
 // ------------------------------------------------------------------------
 // Block DFT on the matrix cores (precision study): Z = F X F with
 // F[k][m] = exp(-2 pi i k m / 32), as two 32x32x32 real GEMM stages per
@@ -387,7 +409,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 
     const int gb = CONC ? 0 : xcd_remap(blockIdx.x, total);
     {
-        const FrameJob fj = CONC ? js.one : job_at(js, gb, &FrameJob::g_blk);
+        int wbi = 0;
+        const FrameJob fj = CONC ? wave_job(js, step, bi0, wbi) : job_at(js, gb, &FrameJob::g_blk);
         if (fj.H == 0) return;   // empty job (stale batch table)
         const int H = fj.H, W = fj.W;
         const int64_t pitch = fj.vpitch, out_pitch = fj.pitch;
@@ -397,7 +420,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         uint8_t* __restrict__ out_u8 = fj.out_u8;
         const int nbw = W >> 2;
         const int blk = gb - fj.g_blk;
-        const int bi = CONC ? bi0 + (int)blockIdx.x : blk / nbw;
+        const int bi = CONC ? wbi : blk / nbw;
         const int bj = CONC ? step - 5 * bi : blk - bi * nbw;
 
         // 1. gather: lane (h, c) holds support rows m = i + 16 h of column c.
@@ -601,11 +624,11 @@ hipError_t launch_fsr_tables(FsrTables* t, double rho, hipStream_t s) {
 }
 
 hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
-                      const FsrTables* tables, hipStream_t s) {
+                      const FsrTables* tables, hipStream_t s, const FrameJob* host_frames) {
     if (total_blocks <= 0) return hipSuccess;
     const size_t shmem = sizeof(float4) * (size_t)p.iters;
     const bool conc = p.concealed_weight > 0.0;
-    if (conc && js.n != 0) return hipErrorInvalidValue;   // single frames only
+    if (conc && js.n != 0 && !host_frames) return hipErrorInvalidValue;
     if (conc && p.pairs) return hipErrorInvalidValue;     // not combined
     auto kernel = fsr_block_kernel<RFSR_PREC_FP64, false, false>;
     if (p.pairs) {
@@ -625,15 +648,22 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
                            p.gamma, p.proj_weight, p.overwrite, 0.0, 0, 0);
         return hipGetLastError();
     }
-    // wavefront: step t holds the blocks with 5 bi + bj = t
-    const int nbh = js.one.H / kBlock, nbw = js.one.W / kBlock;
-    const int steps = 5 * (nbh - 1) + nbw;
+    // wavefront: step t holds the blocks with 5 bi + bj = t of every frame
+    const int nf = js.n == 0 ? 1 : js.n;
+    const FrameJob* fr = js.n == 0 ? &js.one : host_frames;
+    int steps = 0;
+    for (int f = 0; f < nf; ++f) steps = max(steps, wave_steps(fr[f].H, fr[f].W));
     for (int t = 0; t < steps; ++t) {
-        const int lo = t - (nbw - 1) > 0 ? (t - (nbw - 1) + 4) / 5 : 0;
-        const int hi = min(nbh - 1, t / 5);
-        if (hi < lo) continue;
-        hipLaunchKernelGGL(kernel, dim3(hi - lo + 1), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
-                           p.gamma, p.proj_weight, p.overwrite, p.concealed_weight, t, lo);
+        int grid = 0, lo0 = 0;
+        for (int f = 0; f < nf; ++f) {
+            int lo, hi;
+            wave_rows(fr[f].H, fr[f].W, t, lo, hi);
+            if (hi >= lo) grid += hi - lo + 1;
+            if (f == 0) lo0 = lo;
+        }
+        if (grid == 0) continue;
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
+                           p.gamma, p.proj_weight, p.overwrite, p.concealed_weight, t, lo0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

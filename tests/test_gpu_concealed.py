@@ -72,8 +72,23 @@ def test_concealed_recursive_frame_against_oracle():
     assert abs(dp) <= PSNR_TOL
 
 
-def test_batch_refuses_concealed_weighting():
+def test_batch_concealed_equals_single_frames():
+    """The batch runs every frame's wavefront in shared steps: each frame's
+    result equals the single-frame wavefront, bit for bit."""
     R = need_gpu()
-    c = torch.zeros((16, 16), dtype=torch.uint8, device="cuda")
-    with pytest.raises(R.RfsrError):
-        R.Batch([R.BatchFrame(c, c)], R.MEParams(), R.FSRParams(concealed_weight=0.5)).run()
+    me, fsr = R.MEParams(search=5, check="nnc_frmc"), R.FSRParams(iters=30, concealed_weight=0.5)
+    sizes = [(64, 64, 3), (32, 96, 1), (96, 32, 0), (16, 24, 2), (48, 48, 3)]
+    streams = []
+    for i, (H, W, nref) in enumerate(sizes):
+        rng = np.random.default_rng(700 + i)
+        frames, _ = synth.video_translate_edges(nref + 1, H, W, rng, max_step=2, n_edges=2)
+        masks = synth.mask_sequence("dynamic", nref + 1, H, W, rng)
+        meas = synth.measured(frames, masks)
+        refs = [(dev(frames[nref - 1 - k]), dev(meas[nref - 1 - k]), dev(masks[nref - 1 - k])) for k in range(nref)]
+        streams.append((dev(meas[nref]), dev(masks[nref]), refs))
+    singles = [tuple(host(t).copy() for t in R.reconstruct_frame(c, m, r, me, fsr)) for c, m, r in streams]
+    frames = [R.BatchFrame(c, m, tuple(r), out_u8=torch.empty_like(c)) for c, m, r in streams]
+    outs = R.Batch(frames, me, fsr).run()
+    for i, ((o, u), (so, su)) in enumerate(zip(outs, singles)):
+        assert np.array_equal(host(o), so), i
+        assert np.array_equal(host(u), su), i
