@@ -144,8 +144,9 @@ typedef enum {
 enum {
     RFSR_CNT_FORWARD_COSTS = 0,   /* forward template costs evaluated          */
     RFSR_CNT_CHECK_COSTS = 1,     /* reverse template costs evaluated by the
-                                     check (RME, RMC, FRMC; FRMC/RMC stop at
-                                     the first losing candidate)               */
+                                     check (RME, RMC, FRMC; RMC stops at the
+                                     first losing candidate, FRMC after the
+                                     first offset row that holds one)          */
     RFSR_CNT_CHECKED_PIXELS = 2,  /* pixels that entered the RMC/FRMC test     */
     RFSR_CNT_ACCEPTED = 3,        /* accepted pixels                           */
     RFSR_NCOUNTERS = 4

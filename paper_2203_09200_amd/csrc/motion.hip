@@ -359,26 +359,21 @@ __device__ __forceinline__ bool projectable(const RefJob& j, int y, int x, int a
     return j.cur_mask[(int64_t)y * j.pitch + x] == 0 && j.ref_mask[(int64_t)(y + a) * j.pitch + (x + b)] != 0;
 }
 
-// RMC (DENSE, offsets [-rr, rr]^2) and FRMC ({-7,-3,-1,0,1,3,7}^2) at pixel p
-// with vector (a, b): accept iff S(p,v)/n(p) < S(p+d, v-d)/n(p+d) for every
-// red d with p+d in the frame.  Reds are tried in raster order and the test
-// stops at the first loser.  evals counts the red costs evaluated.
-template <bool DENSE>
-__device__ __forceinline__ bool reverse_test(const RefJob& j, int py, int px, int a, int b, int rr,
-                                             unsigned long long& evals) {
+// RMC at pixel p with vector (a, b), offsets [-rr, rr]^2: accept iff
+// S(p,v)/n(p) < S(p+d, v-d)/n(p+d) for every red d with p+d in the frame.
+// Reds are tried in raster order and the test stops at the first loser.
+// evals counts the red costs evaluated.
+__device__ __forceinline__ bool rmc_test(const RefJob& j, int py, int px, int a, int b, int rr,
+                                         unsigned long long& evals) {
     uint32_t r[4];
     ref_template(j, py + a, px + b, r);
     const uint32_t Sg = j.cost[(int64_t)py * j.cpitch + px];
     const uint32_t ng = j.nmap[(int64_t)py * j.W + px];
     bool ok = true;
-    // FRMC offsets {-7,-3,-1,0,1,3,7}: sign(i-3) * (2^|i-3| - 1)
-    const int n1 = DENSE ? 2 * rr + 1 : 7;
-    for (int iy = 0; iy < n1 && ok; ++iy) {
-        const int dy = DENSE ? iy - rr : (iy < 3 ? -1 : 1) * ((1 << abs(iy - 3)) - 1);
+    for (int dy = -rr; dy <= rr && ok; ++dy) {
         const int sy = py + dy;
         if ((unsigned)sy >= (unsigned)j.H) continue;
-        for (int ix = 0; ix < n1; ++ix) {
-            const int dx = DENSE ? ix - rr : (ix < 3 ? -1 : 1) * ((1 << abs(ix - 3)) - 1);
+        for (int dx = -rr; dx <= rr; ++dx) {
             const int sx = px + dx;
             if ((dy | dx) == 0 || (unsigned)sx >= (unsigned)j.W) continue;
             const uint32_t S = rev_cost(j, r, sy, sx);
@@ -388,6 +383,50 @@ __device__ __forceinline__ bool reverse_test(const RefJob& j, int py, int px, in
         }
     }
     return ok;
+}
+
+// FRMC at pixel p with vector (a, b), offsets {-7,-3,-1,0,1,3,7}^2: the
+// acceptance rule of rmc_test, organised for memory-level parallelism.  The
+// seven red candidates of one offset row are evaluated together: their 28
+// window reads have no branch between them (the padded window plane covers
+// offsets up to +-kPad, and an out-of-frame candidate only drops out of the
+// comparison).  The test stops after the first row that holds a loser;
+// evals counts the in-frame red costs of the rows evaluated.
+__device__ __forceinline__ bool frmc_test(const RefJob& j, int py, int px, int a, int b,
+                                          unsigned long long& evals) {
+    static_assert(kPad >= 7 + 2, "window plane border must cover the FRMC offsets and the template");
+    constexpr int kOff[7] = {-7, -3, -1, 0, 1, 3, 7};
+    uint32_t r[4];
+    ref_template(j, py + a, px + b, r);
+    const uint32_t Sg = j.cost[(int64_t)py * j.cpitch + px];
+    const uint32_t ng = j.nmap[(int64_t)py * j.W + px];
+    const int Wp = j.W + 2 * kPad;
+#pragma unroll
+    for (int iy = 0; iy < 7; ++iy) {
+        const int sy = py + kOff[iy];
+        if ((unsigned)sy >= (unsigned)j.H) continue;
+        const uint2* row = j.fm + (int64_t)(sy - 1 + kPad) * Wp + (px + kPad);
+        const uint8_t* nrow = j.nmap + (int64_t)sy * j.W;
+        bool lose = false;
+#pragma unroll
+        for (int ix = 0; ix < 7; ++ix) {
+            if (iy == 3 && ix == 3) continue;   // the green candidate
+            const int dx = kOff[ix];
+            const int sx = px + dx;
+            const bool in = (unsigned)sx < (unsigned)j.W;
+            uint32_t S = 0;
+#pragma unroll
+            for (int dy = 0; dy < 4; ++dy) {
+                const uint2 v = row[dy * Wp + dx];
+                S = __builtin_amdgcn_sad_u8(v.x, r[dy] & v.y, S);
+            }
+            const uint32_t n = nrow[clampi(sx, 0, j.W - 1)];
+            evals += in;
+            lose |= in & (S * ng <= Sg * n);   // no short circuit: the reads stay unconditional
+        }
+        if (lose) return false;
+    }
+    return true;
 }
 
 // RMC / FRMC over every pixel (stand-alone checks); with a reference mask
@@ -406,7 +445,7 @@ __global__ __launch_bounds__(256) void rmc_kernel(Jobs<RefJob> js, int rr,
         bool ok = projectable(j, py, px, a, b);
         if (ok) {
             checked = 1;
-            ok = reverse_test<DENSE>(j, py, px, a, b, rr, evals);
+            ok = DENSE ? rmc_test(j, py, px, a, b, rr, evals) : frmc_test(j, py, px, a, b, evals);
         }
         j.accept[o] = ok;
         accepted = ok;
@@ -466,7 +505,7 @@ __global__ __launch_bounds__(256) void frmc_tile_kernel(Jobs<RefJob> js,
         const int e = s_list[i];
         const int py = e / j.W, px = e - py * j.W;
         const int64_t o = (int64_t)py * j.opitch + px;
-        const bool ok = reverse_test<false>(j, py, px, j.mv_a[o], j.mv_b[o], 0, evals);
+        const bool ok = frmc_test(j, py, px, j.mv_a[o], j.mv_b[o], evals);
         j.accept[o] = ok;
         accepted += ok;
     }
