@@ -154,27 +154,51 @@ __global__ __launch_bounds__(256) void me_forward_kernel(Jobs<RefJob> js, int to
     const int ty = tid >> 4, tx = tid & 15;
     const uint8_t* __restrict__ ref = j.ref;
 
-    // Stage the four shifted copies of the clamped reference window.
+    // Stage the clamped reference window: the unshifted copy (and one more
+    // dword per row, kept in s_tail) from global memory, then the copies
+    // shifted by 1..3 bytes built from it in LDS.  Both loops are unrolled
+    // with the element index clamped to the last one, so every thread issues
+    // all its loads before the first wait (threads past the end rewrite the
+    // last element with the same value).
+    __shared__ uint32_t s_tail[G::ROWS];
     {
         constexpr int DW = G::ROWB / 4;        // dwords per copy row
-        constexpr int TOTAL = 4 * G::ROWS * DW;
+        constexpr int T0 = G::ROWS * (DW + 1);
         const int gy0 = y0 - 1 - R, gx0 = x0 - 1 - R;
-        for (int e = tid; e < TOTAL; e += 256) {
-            const int a = e / (G::ROWS * DW);
-            const int rem = e - a * (G::ROWS * DW);
-            const int tr = rem / DW, kd = rem - tr * DW;
+#pragma unroll
+        for (int it = 0; it < (T0 + 255) / 256; ++it) {
+            const int e = min(tid + 256 * it, T0 - 1);
+            const int tr = e / (DW + 1), kd = e - tr * (DW + 1);
             const int64_t rowoff = (int64_t)clampi(gy0 + tr, 0, H - 1) * pitch;
             uint32_t v = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int gx = clampi(gx0 + 4 * kd + b + a, 0, W - 1);
+                const int gx = clampi(gx0 + 4 * kd + b, 0, W - 1);
                 v |= (uint32_t)ref[rowoff + gx] << (8 * b);
             }
-            reinterpret_cast<uint32_t*>(s_ref + a * G::COPY + tr * G::ROWB)[kd] = v;
+            if (kd < DW) reinterpret_cast<uint32_t*>(s_ref + tr * G::ROWB)[kd] = v;
+            else s_tail[tr] = v;
+        }
+        __syncthreads();
+        constexpr int T1 = 3 * G::ROWS * DW;
+#pragma unroll
+        for (int it = 0; it < (T1 + 255) / 256; ++it) {
+            const int e = min(tid + 256 * it, T1 - 1);
+            const int a = 1 + e / (G::ROWS * DW);
+            const int rem = e - (a - 1) * (G::ROWS * DW);
+            const int tr = rem / DW, kd = rem - tr * DW;
+            const uint32_t* c0 = reinterpret_cast<const uint32_t*>(s_ref + tr * G::ROWB);
+            const uint32_t lo = c0[kd];
+            const uint32_t hi = kd + 1 < DW ? c0[kd + 1] : s_tail[tr];
+            // bytes a..a+3 of (hi:lo): window bytes 4 kd + a .. 4 kd + a + 3
+            reinterpret_cast<uint32_t*>(s_ref + a * G::COPY + tr * G::ROWB)[kd] =
+                __builtin_amdgcn_alignbit(hi, lo, 8 * a);
         }
     }
 
     // Template of the current frame: measured bytes, 0 where unmeasured.
+    // Mask and value are read at clamped (in-bounds) positions without
+    // branches, so all 32 loads are in flight together.
     const int py = y0 + ty, px = x0 + tx;
     uint32_t t[4], tz[4];
     uint32_t n = 0, nz = 0;
@@ -185,16 +209,14 @@ __global__ __launch_bounds__(256) void me_forward_kernel(Jobs<RefJob> js, int to
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int x = px - 1 + i;
-            if (inside(y, x, H, W)) {
-                const int64_t off = (int64_t)y * pitch + x;
-                if (j.cur_mask[off]) {
-                    const uint32_t v = j.cur[off];
-                    tv |= v << (8 * i);
-                    zv |= (v == 0 ? 0xFFu : 0u) << (8 * i);
-                    n += 1;
-                    nz += (v == 0);
-                }
-            }
+            const int64_t off = (int64_t)clampi(y, 0, H - 1) * pitch + clampi(x, 0, W - 1);
+            const uint32_t mk = j.cur_mask[off];
+            const uint32_t v = j.cur[off];
+            const bool meas = inside(y, x, H, W) && mk != 0;
+            tv |= (meas ? v : 0u) << (8 * i);
+            zv |= (meas && v == 0 ? 0xFFu : 0u) << (8 * i);
+            n += meas;
+            nz += meas && v == 0;
         }
         t[dy] = tv;
         tz[dy] = zv;
