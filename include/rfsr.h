@@ -18,7 +18,8 @@
  *  - H and W must be positive multiples of 4 (the FSR block size, hence also
  *    of the 2x2 quarter-sampling cell) and at most 16384.
  *  - Masks hold 0 (not measured) or 1 (measured).  Measured-frame values at
- *    unmeasured positions are never read, so they may hold anything.
+ *    unmeasured positions never influence a result (kernels may load them
+ *    at in-bounds addresses and discard them), so they may hold anything.
  *  - Motion vectors are (alpha, beta) = (row offset, column offset), int8.
  *  - Calls on different streams do not share state and may run concurrently
  *    as long as their workspaces differ.
@@ -161,7 +162,7 @@ size_t rfsr_workspace_bytes(int32_t H, int32_t W, int32_t nref,
 /* Forward motion estimation of the current frame against one reference
  * reconstruction, followed by the consistency check `me->check`
  * (Sec. 2.2, Sec. 3.1).
- *   cur        uint8 H x W measured frame f_t (read only where cur_mask==1)
+ *   cur        uint8 H x W measured frame f_t (used only where cur_mask==1)
  *   cur_mask   uint8 H x W mask b_t
  *   ref_recon  uint8 H x W reconstruction of the past frame
  *   mv         int8 [2][H][W] out: plane 0 alpha (rows), plane 1 beta (cols);
@@ -179,7 +180,7 @@ rfsr_status rfsr_motion_check(const uint8_t* cur, const uint8_t* cur_mask,
                               void* workspace, size_t ws_bytes, void* stream);
 
 /* Block-parallel FSR of one frame (Sec. 2.1; Sec. 3.2 for classes).
- *   values  float32 H x W sample values, read only where cls > 0
+ *   values  float32 H x W sample values, used only where cls > 0
  *   cls     uint8 H x W: 0 unknown, 1 measured, 2 projected (others = 0)
  *   out     float32 H x W out: Re of the model, then the overwrite rule;
  *           not clamped
@@ -197,7 +198,7 @@ rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32
  * accepted vectors point to (averaged over references, Sec. 2.2); FSR with
  * measured and projected samples; overwrite; quantisation.
  *   ref_recon, ref_meas, ref_mask: HOST arrays of nref device pointers,
- *     index k = lag k+1 (uint8 H x W each; ref_meas read only where
+ *     index k = lag k+1 (uint8 H x W each; ref_meas used only where
  *     ref_mask == 1).  May be NULL when nref == 0 (single-frame FSR).
  *   out     float32 H x W out; out_u8 uint8 H x W out (nullable)
  *   stage_events: NULL, or a HOST array of 4 events (from rfsr_event_create)

@@ -78,3 +78,29 @@ def test_sequence_free_running_psnr():
         p_o = O.psnr(frames[t], ora[t]["out"], 8)
         print(f"t={t}: gpu {p_g:.4f} dB oracle {p_o:.4f} dB")
         assert abs(p_g - p_o) <= PSNR_TOL
+
+
+@pytest.mark.parametrize("check", ["nnc_frmc", "rme", "rmc"])
+def test_frame_ignores_unmeasured_values(check):
+    """Values of the current and the reference measured frames at unmeasured
+    positions never influence a result: random bytes there (instead of the
+    zeros the quarter sampling leaves) give bit-identical motion fields,
+    decisions and reconstructions.  Ragged 44x60 frame (not a multiple of the
+    16x16 ME tile), three references."""
+    R = need_gpu()
+    rng = np.random.default_rng(44)
+    H, W = 44, 60
+    frames, _ = synth.video_translate_edges(4, H, W, rng, max_step=3, n_edges=3)
+    masks = synth.mask_sequence("dynamic", 4, H, W, rng)
+    meas = synth.measured(frames, masks)
+    dirty = [np.where(m == 1, f, rng.integers(0, 256, f.shape)).astype(np.uint8) for f, m in zip(meas, masks)]
+    recon = [frames[2 - k] for k in range(3)]
+    me, fsr = R.MEParams(search=6, check=check), R.FSRParams(iters=30)
+    outs = []
+    for src in (meas, dirty):
+        refs = [(dev(recon[k]), dev(src[2 - k]), dev(masks[2 - k])) for k in range(3)]
+        o, u = R.reconstruct_frame(dev(src[3]), dev(masks[3]), refs, me, fsr)
+        mv, acc, cost = R.motion_check(dev(src[3]), dev(masks[3]), dev(recon[0]), me)
+        outs.append([host(x) for x in (o, u, mv, acc, cost)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
