@@ -144,20 +144,20 @@ def run_multistream(a, dev):
 
     t_last = (ss.t - 1) % T
     slot = (ss.t - 1) % ss.SLOTS
-    q = float(np.mean([psnr(data[s][0][t_last], ss.out[s][slot].cpu().numpy(), 8)
-                       for s in range(len(sizes))]))
+    psnr_mean = float(np.mean([psnr(data[s][0][t_last], ss.out[s][slot].cpu().numpy(), 8)
+                               for s in range(len(sizes))]))
 
     plain = None
     if a.plain:
         seqs = [R.Sequence(h, w, me, fsr, device=dev) for h, w in sizes]
         for t in range(4):   # fill the rings
-            for s, q in enumerate(seqs):
-                q.push(meas[s][t % T], masks[s][t % T])
+            for s, seq in enumerate(seqs):
+                seq.push(meas[s][t % T], masks[s][t % T])
         torch.cuda.synchronize()
         p0 = time.perf_counter()
         for k in range(a.steps):
-            for s, q in enumerate(seqs):
-                q.push(meas[s][(4 + k) % T], masks[s][(4 + k) % T])
+            for s, seq in enumerate(seqs):
+                seq.push(meas[s][(4 + k) % T], masks[s][(4 + k) % T])
         torch.cuda.synchronize()
         pe = time.perf_counter() - p0
         plain = {"value": round(px_step * a.steps / pe / 1e6, 3), "unit": "HR Mpix/s",
@@ -180,7 +180,7 @@ def run_multistream(a, dev):
                                + (f", concealed weighting {a.concealed}" if a.concealed else ""),
                    "streams": len(sizes), "hr_px_per_step": px_step, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
-        "psnr_db": round(q, 3),
+        "psnr_db": round(psnr_mean, 3),
         "plain": plain,
     }
     print(json.dumps(res))
