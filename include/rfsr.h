@@ -204,6 +204,10 @@ rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32
  *   stage_events: NULL, or a HOST array of 4 events (from rfsr_event_create)
  *     recorded on `stream` at: [0] start, [1] after ME and checks,
  *     [2] after projection, [3] after FSR.
+ * The frame runs as a batch of one (rfsr_reconstruct_batch below): its job
+ * tables are written into the last 1 KB of the workspace by a kernel, so the
+ * call enqueues only kernels and event records, and each stage is one launch
+ * over all references.
  * Errors: as rfsr_motion_check and fsr_blocks. */
 rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
                                    const uint8_t* const* ref_recon,

@@ -302,6 +302,71 @@ BatchPlan plan_batch(const rfsr_frame_desc* d, int n, const rfsr_me_params& me, 
     return p;
 }
 
+// Host image of a batch's job tables: header (with the batch key) |
+// FrameJob[n] | RefJob[total references].
+void write_image(const rfsr_frame_desc* frames, int n, const rfsr_me_params& me, uint8_t* ws,
+                 const BatchLayout& L, uint8_t* img) {
+    const BatchPlan p = plan_batch(frames, n, me, ws, L);
+    memset(img, 0, L.table_bytes);
+    TableHeader hdr;
+    memset(&hdr, 0, sizeof(hdr));
+    hdr.key = batch_key(frames, n, me.check, ws);
+    hdr.n_frames = n;
+    hdr.n_refs = (int)p.refs.size();
+    memcpy(img, &hdr, sizeof(hdr));
+    memcpy(img + kTableHeader, p.frames.data(), sizeof(FrameJob) * p.frames.size());
+    if (!p.refs.empty()) memcpy(img + L.refs_offset, p.refs.data(), sizeof(RefJob) * p.refs.size());
+}
+
+// Job-table image of one frame with up to three references, small enough to
+// travel as a kernel argument.
+constexpr size_t kFrameTable = 1024;
+static_assert(kTableHeader + sizeof(FrameJob) + 3 * sizeof(RefJob) <= kFrameTable, "frame job table");
+struct FrameTableImage {
+    uint32_t w[kFrameTable / 4];
+};
+
+// Writes a frame's job-table image into its workspace, in stream order and
+// without a copy: one workgroup, one dword per thread.
+__global__ __launch_bounds__(256) void write_table_kernel(FrameTableImage img, uint32_t* __restrict__ dst) {
+    dst[threadIdx.x] = img.w[threadIdx.x];
+}
+
+// The launch chain of a batch whose job-table image is at `img` on the
+// device: tables, window planes, forward ME and checks over all (frame,
+// reference) pairs, projection, FSR; stage events around the stages.  With
+// `upload`, that image is first written to `img` (after the start event).
+hipError_t run_batch(const rfsr_frame_desc* frames, int n, const rfsr_me_params& me,
+                     const rfsr_fsr_params& fsr, const uint8_t* img, const FrameTableImage* upload,
+                     void* const* stage_events, uint8_t* ws, const BatchLayout& L, hipStream_t s) {
+    const BatchPlan p = plan_batch(frames, n, me, ws, L);   // grid sizes
+    const unsigned long long key = batch_key(frames, n, me.check, ws);
+    const Jobs<FrameJob> jf = table<FrameJob>(img, kTableHeader, n, key);
+    const Jobs<RefJob> jr = table<RefJob>(img, L.refs_offset, (int)p.refs.size(), key);
+    FsrTables* tab = reinterpret_cast<FsrTables*>(ws);
+    hipError_t e = hipSuccess;
+    auto record = [&](int k) {
+        if (stage_events && e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s);
+    };
+    record(0);
+    if (e == hipSuccess && upload) {
+        hipLaunchKernelGGL(write_table_kernel, dim3(1), dim3(256), 0, s, *upload,
+                           reinterpret_cast<uint32_t*>(const_cast<uint8_t*>(img)));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_fsr_tables(tab, fsr.rho, s);
+    if (e == hipSuccess && !p.refs.empty()) {
+        e = launch_windows(jf, p.win, s);
+        if (e == hipSuccess) e = launch_motion(jr, p.tiles, p.px_refs, p.frmc, me, nullptr, s);
+    }
+    record(1);
+    if (e == hipSuccess) e = launch_project(jf, p.px_frames, s);
+    record(2);
+    if (e == hipSuccess) e = launch_fsr(jf, p.blocks, fsr, tab, s, p.frames.data());
+    record(3);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -311,7 +376,7 @@ size_t rfsr_workspace_bytes(int32_t H, int32_t W, int32_t nref, const rfsr_me_pa
     if (check_shape(H, W, W) != RFSR_OK || nref < 0 || nref > 3) return 0;
     if (me && check_me(me) == RFSR_EINVAL) return 0;
     if (fsr && check_fsr(fsr) == RFSR_EINVAL) return 0;
-    return single_ws(H, W, nref > 0 ? nref : 1);
+    return single_ws(H, W, nref > 0 ? nref : 1) + kFrameTable;
 }
 
 rfsr_status rfsr_motion_check(const uint8_t* cur, const uint8_t* cur_mask, const uint8_t* ref_recon,
@@ -412,30 +477,33 @@ rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, 
     if (st != RFSR_OK) return st;
     if ((st = check_me(me)) != RFSR_OK) return st;
     if ((st = check_fsr(fsr)) != RFSR_OK) return st;
-    if ((st = check_ws(workspace, ws_bytes, single_ws(H, W, nref > 0 ? nref : 1))) != RFSR_OK) return st;
+    const size_t scratch = single_ws(H, W, nref > 0 ? nref : 1);
+    if ((st = check_ws(workspace, ws_bytes, scratch + kFrameTable)) != RFSR_OK) return st;
 
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    // A batch of one frame: its job tables (frame + references) go to the
+    // end of the workspace, written in stream order by a one-workgroup
+    // kernel, and every stage is one launch over all references.
+    rfsr_frame_desc d;
+    memset(&d, 0, sizeof(d));
+    d.cur = cur;
+    d.cur_mask = cur_mask;
+    for (int k = 0; k < nref; ++k) {
+        d.ref_recon[k] = ref_recon[k];
+        d.ref_meas[k] = ref_meas[k];
+        d.ref_mask[k] = ref_mask[k];
+    }
+    d.out = out;
+    d.out_u8 = out_u8;
+    d.nref = nref;
+    d.H = H;
+    d.W = W;
+    d.pitch = pitch;
     uint8_t* ws = static_cast<uint8_t*>(workspace);
-    FsrTables* tab = reinterpret_cast<FsrTables*>(ws);
-    const bool windows = nref > 0 && check_needs_windows(me->check);
-    FrameJob fj;
-    RefJob rj[3];
-    make_jobs(f, ws + align256(sizeof(FsrTables)), windows, fj, rj);
-    hipError_t e = hipSuccess;
-    auto record = [&](int k) {
-        if (stage_events && e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s);
-    };
-    record(0);
-    if (e == hipSuccess) e = launch_fsr_tables(tab, fsr->rho, s);
-    if (e == hipSuccess && windows) e = launch_windows(single(fj), win_groups(H, W), s);
-    for (int k = 0; k < nref && e == hipSuccess; ++k)
-        e = launch_motion(single(rj[k]), me_tiles(H, W), px_groups(H, W), frmc_groups(H, W), *me, nullptr, s);
-    record(1);
-    if (e == hipSuccess) e = launch_project(single(fj), px_groups(H, W), s);
-    record(2);
-    if (e == hipSuccess) e = launch_fsr(single(fj), (H / kBlock) * (W / kBlock), *fsr, tab, s);
-    record(3);
-    return from_hip(e);
+    const BatchLayout L(&d, 1);   // L.total <= scratch, L.table_bytes <= kFrameTable
+    FrameTableImage img;
+    write_image(&d, 1, *me, ws, L, reinterpret_cast<uint8_t*>(img.w));
+    return from_hip(run_batch(&d, 1, *me, *fsr, ws + scratch, &img, stage_events, ws, L,
+                              static_cast<hipStream_t>(stream)));
 }
 
 size_t rfsr_batch_workspace_bytes(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
@@ -459,17 +527,8 @@ rfsr_status rfsr_batch_write_tables(const rfsr_frame_desc* frames, int32_t n, co
     if (!workspace || ((uintptr_t)workspace & 255u) != 0) return RFSR_EWORKSPACE;
     const BatchLayout L(frames, n);
     if (!image || image_bytes < L.table_bytes) return RFSR_EINVAL;
-    const BatchPlan p = plan_batch(frames, n, *me, static_cast<uint8_t*>(const_cast<void*>(workspace)), L);
-    uint8_t* img = static_cast<uint8_t*>(image);
-    memset(img, 0, L.table_bytes);
-    TableHeader hdr;
-    memset(&hdr, 0, sizeof(hdr));
-    hdr.key = batch_key(frames, n, me->check, workspace);
-    hdr.n_frames = n;
-    hdr.n_refs = (int)p.refs.size();
-    memcpy(img, &hdr, sizeof(hdr));
-    memcpy(img + kTableHeader, p.frames.data(), sizeof(FrameJob) * p.frames.size());
-    if (!p.refs.empty()) memcpy(img + L.refs_offset, p.refs.data(), sizeof(RefJob) * p.refs.size());
+    write_image(frames, n, *me, static_cast<uint8_t*>(const_cast<void*>(workspace)), L,
+                static_cast<uint8_t*>(image));
     return RFSR_OK;
 }
 
@@ -488,30 +547,9 @@ rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n, con
     const BatchLayout L(frames, n);
     if ((st = check_ws(workspace, ws_bytes, L.total)) != RFSR_OK) return st;
 
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    uint8_t* ws = static_cast<uint8_t*>(workspace);
-    const BatchPlan p = plan_batch(frames, n, *me, ws, L);   // grid sizes
-    const unsigned long long key = batch_key(frames, n, me->check, workspace);
-    const uint8_t* img = static_cast<const uint8_t*>(job_tables);
-    const Jobs<FrameJob> jf = table<FrameJob>(img, kTableHeader, n, key);
-    const Jobs<RefJob> jr = table<RefJob>(img, L.refs_offset, (int)p.refs.size(), key);
-    FsrTables* tab = reinterpret_cast<FsrTables*>(ws);
-    hipError_t e = hipSuccess;
-    auto record = [&](int k) {
-        if (stage_events && e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s);
-    };
-    record(0);
-    if (e == hipSuccess) e = launch_fsr_tables(tab, fsr->rho, s);
-    if (e == hipSuccess && !p.refs.empty()) {
-        e = launch_windows(jf, p.win, s);
-        if (e == hipSuccess) e = launch_motion(jr, p.tiles, p.px_refs, p.frmc, *me, nullptr, s);
-    }
-    record(1);
-    if (e == hipSuccess) e = launch_project(jf, p.px_frames, s);
-    record(2);
-    if (e == hipSuccess) e = launch_fsr(jf, p.blocks, *fsr, tab, s, p.frames.data());
-    record(3);
-    return from_hip(e);
+    return from_hip(run_batch(frames, n, *me, *fsr, static_cast<const uint8_t*>(job_tables), nullptr,
+                              stage_events, static_cast<uint8_t*>(workspace), L,
+                              static_cast<hipStream_t>(stream)));
 }
 
 size_t rfsr_quality_workspace_bytes(int32_t H, int32_t W, int32_t border) {
