@@ -9,6 +9,9 @@ rho = 0.7, gamma = 0.5, 100 iterations, three reference frames.
 One step = the causal recursion over the 16-frame sequence (every frame runs
 ME + check against up to three references, projection, FSR, overwrite and
 quantisation on the GPU).  Inputs are resident in HBM before timing.
+Consecutive frames are pipelined (results unchanged): the motion path of a
+frame's lag-2 and lag-3 references runs on a side stream during the previous
+frame's FSR (--no-pipeline: one frame after the other).
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
 
@@ -199,6 +202,8 @@ def main(argv=None):
     ap.add_argument("--search", type=int, default=9)
     ap.add_argument("--check", default="nnc_frmc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="c2: no overlap of consecutive frames (each frame's motion path after the previous frame)")
     ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
                     help="c2: the metric's 1080p recursion (default); c4: 48 streams of uneven "
                          "size advanced one time step per batch")
@@ -245,17 +250,15 @@ def main(argv=None):
     outs_u8 = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(F)]
     me = R.MEParams(search=a.search, check=a.check)
     fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs, concealed_weight=a.concealed)
-    ws = R.Workspace(dev)
     stream = torch.cuda.current_stream()
+    seq = R.Sequence(H, W, me, fsr, device=dev, pipelined=not a.no_pipeline)
+    torch.cuda.synchronize()   # inputs resident before any frame is enqueued
 
     def step(events=None):
-        ring = []
+        seq.reset()
         for t in range(F):
-            refs = list(reversed(ring[-3:]))
-            R.reconstruct_frame(d_meas[t], d_mask[t], refs, me, fsr, out=outs[t], out_u8=outs_u8[t],
-                                stage_events=None if events is None else events[t], workspace=ws,
-                                stream=stream)
-            ring.append((outs_u8[t], d_meas[t], d_mask[t]))
+            seq.push(d_meas[t], d_mask[t], stage_events=None if events is None else events[t], stream=stream,
+                     out=outs[t], out_u8=outs_u8[t])
 
     for _ in range(a.warmup):
         step()
@@ -271,12 +274,14 @@ def main(argv=None):
     elapsed = time.perf_counter() - t0
     print(f"# timed {a.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
+    # frame latency: completion of frame t after the completion of frame t-1
+    # (its lag-1 reference); the first frame of a step from its own start
     lat, me_ms, proj_ms, fsr_ms = [], [], [], []
     lat_steady = []
     for k in range(a.steps):
         for t in range(F):
             e = ev[k][t]
-            tot = e[0].elapsed_ms(e[3])
+            tot = (ev[k][t - 1][3] if t > 0 else e[0]).elapsed_ms(e[3])
             lat.append(tot)
             if t >= 3:
                 lat_steady.append(tot)
@@ -324,13 +329,16 @@ def main(argv=None):
                                + ("" if a.precision == "fp64" else f", block DFT {a.precision}")
                                + (", conjugate-pair FSR" if a.pairs else "")
                                + (f", concealed weighting {a.concealed}" if a.concealed else ""),
-                   "frames": F, "height": H, "width": W, "parallelism": "single GPU"},
+                   "frames": F, "height": H, "width": W, "parallelism": "single GPU",
+                   "pipelined": not a.no_pipeline},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "p50_steady": round(percentile(lat_steady, 50), 3) if lat_steady else None,
                        "p99_steady": round(percentile(lat_steady, 99), 3) if lat_steady else None},
         "stage_ms_mean": {"me_and_check": round(float(np.mean(me_ms)), 4),
                           "projection": round(float(np.mean(proj_ms)), 4),
-                          "fsr": round(float(np.mean(fsr_ms)), 4)},
+                          "fsr": round(float(np.mean(fsr_ms)), 4),
+                          "note": ("me_and_check: the lag-1 reference (lags 2-3 run on a side stream during the "
+                                   "previous frame's FSR)" if not a.no_pipeline else "all references")},
         "psnr_db": round(q, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -205,9 +205,9 @@ rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32
  *     recorded on `stream` at: [0] start, [1] after ME and checks,
  *     [2] after projection, [3] after FSR.
  * The frame runs as a batch of one (rfsr_reconstruct_batch below): its job
- * tables are written into the last 1 KB of the workspace by a kernel, so the
- * call enqueues only kernels and event records, and each stage is one launch
- * over all references.
+ * tables are written into a 1 KB slot after the frame's scratch by a kernel,
+ * so the call enqueues only kernels and event records, and each stage is one
+ * launch over all references.
  * Errors: as rfsr_motion_check and fsr_blocks. */
 rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
                                    const uint8_t* const* ref_recon,
@@ -217,6 +217,44 @@ rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, 
                                    const rfsr_me_params* me, const rfsr_fsr_params* fsr,
                                    float* out, uint8_t* out_u8, void* const* stage_events,
                                    void* workspace, size_t ws_bytes, void* stream);
+
+/* The same frame in two calls, so that consecutive frames of a recursion can
+ * overlap (Fig. 1 order and results unchanged).  Frame t+1's references of
+ * lag >= 2 are frames t-1 and t-2, final before frame t is; their motion
+ * path can run on a second stream while frame t's FSR runs, and only the
+ * lag-1 reference (frame t) waits for frame t.
+ *
+ * rfsr_frame_motion: the window plane of the current frame and the forward ME
+ * and consistency check of references first..nref-1 (lags first+1..nref),
+ * into `workspace`.  Arguments as rfsr_reconstruct_frame; 0 <= first <= nref
+ * (first == nref: nothing to do).
+ *
+ * rfsr_frame_finish: the forward ME and check of references 0..first-1, the
+ * projection over all nref references, FSR, overwrite and quantisation, i.e.
+ * the rest of the frame.  With first < nref it requires a preceding
+ * rfsr_frame_motion(..., first, ...) with the same arguments and workspace,
+ * ordered before this call by the caller (same stream, or an event); with
+ * first == nref it is rfsr_reconstruct_frame.  The two calls use separate
+ * 1 KB job-table slots of the workspace (rfsr_workspace_bytes covers both),
+ * so the second may be enqueued while the first is still running; the
+ * workspace must not be used by another frame until the second completes.
+ * Errors: as rfsr_reconstruct_frame; RFSR_EINVAL for first outside 0..nref. */
+rfsr_status rfsr_frame_motion(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
+                              const uint8_t* const* ref_recon,
+                              const uint8_t* const* ref_meas,
+                              const uint8_t* const* ref_mask,
+                              int32_t H, int32_t W, int64_t pitch,
+                              const rfsr_me_params* me, int32_t first,
+                              void* workspace, size_t ws_bytes, void* stream);
+rfsr_status rfsr_frame_finish(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
+                              const uint8_t* const* ref_recon,
+                              const uint8_t* const* ref_meas,
+                              const uint8_t* const* ref_mask,
+                              int32_t H, int32_t W, int64_t pitch,
+                              const rfsr_me_params* me, const rfsr_fsr_params* fsr,
+                              int32_t first, float* out, uint8_t* out_u8,
+                              void* const* stage_events,
+                              void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------- batches ---
  * Many independent streams of recursive reconstruction advance one time step
@@ -300,12 +338,16 @@ rfsr_status rfsr_quality(const uint8_t* ref, const float* test, int32_t H, int32
                          int64_t pitch, int32_t border, double* result,
                          void* workspace, size_t ws_bytes, void* stream);
 
-/* Timing events for stage_events and benchmarks (thin wrappers of HIP
- * events).  rfsr_event_elapsed_ms waits for `stop`. */
+/* Events for stage_events, benchmarks and ordering between streams (thin
+ * wrappers of HIP events).  rfsr_event_elapsed_ms waits for `stop`;
+ * rfsr_event_wait makes work enqueued on `stream` after it wait for the
+ * event's last record (e.g. a frame's stage event [2], after which only its
+ * FSR remains, to start the next frame's early motion path beside that FSR). */
 rfsr_status rfsr_event_create(void** event);
 rfsr_status rfsr_event_destroy(void* event);
 rfsr_status rfsr_event_record(void* event, void* stream);
 rfsr_status rfsr_event_elapsed_ms(void* start, void* stop, float* ms);
+rfsr_status rfsr_event_wait(void* event, void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* rfsr_status_string(int32_t status);

@@ -110,6 +110,15 @@ def lib():
                                          ctypes.c_int64, ctypes.POINTER(_MEParams),
                                          ctypes.POINTER(_FSRParams), _P, _P, ctypes.POINTER(_P),
                                          _P, ctypes.c_size_t, _P]
+    L.rfsr_frame_motion.restype = _STATUS
+    L.rfsr_frame_motion.argtypes = [_P, _P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                    ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                    ctypes.POINTER(_MEParams), ctypes.c_int32, _P, ctypes.c_size_t, _P]
+    L.rfsr_frame_finish.restype = _STATUS
+    L.rfsr_frame_finish.argtypes = [_P, _P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                    ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                    ctypes.POINTER(_MEParams), ctypes.POINTER(_FSRParams), ctypes.c_int32,
+                                    _P, _P, ctypes.POINTER(_P), _P, ctypes.c_size_t, _P]
     L.rfsr_batch_workspace_bytes.restype = ctypes.c_size_t
     L.rfsr_batch_workspace_bytes.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32,
                                              ctypes.POINTER(_MEParams), ctypes.POINTER(_FSRParams)]
@@ -133,6 +142,8 @@ def lib():
     L.rfsr_event_destroy.argtypes = [_P]
     L.rfsr_event_record.restype = _STATUS
     L.rfsr_event_record.argtypes = [_P, _P]
+    L.rfsr_event_wait.restype = _STATUS
+    L.rfsr_event_wait.argtypes = [_P, _P]
     L.rfsr_event_elapsed_ms.restype = _STATUS
     L.rfsr_event_elapsed_ms.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_float)]
     L.rfsr_status_string.restype = ctypes.c_char_p
@@ -257,14 +268,8 @@ def fsr_blocks(values, cls, fsr: FSRParams | None = None, want_u8=True,
     return out, out_u8
 
 
-def reconstruct_frame(cur, cur_mask, refs=(), me: MEParams | None = None,
-                      fsr: FSRParams | None = None, out=None, out_u8=None, stage_events=None,
-                      workspace: Workspace | None = None, stream=None):
-    """One recursive frame (Fig. 1 order).  refs: sequence of
-    (recon uint8, meas uint8, mask uint8) device planes for lags 1..len(refs).
-    Returns (out float32 (H,W), out_u8 uint8 (H,W))."""
-    me = me or MEParams()
-    fsr = fsr or FSRParams()
+def _frame_args(cur, cur_mask, refs, name):
+    """Validated planes of one frame: (H, W, pitch, nref, rr, rm, rk, planes)."""
     _plane(cur, torch.uint8, "cur")
     H, W = cur.shape
     _plane(cur_mask, torch.uint8, "cur_mask", (H, W))
@@ -277,6 +282,27 @@ def reconstruct_frame(cur, cur_mask, refs=(), me: MEParams | None = None,
         for t, nm in ((r, "recon"), (m, "meas"), (b, "mask")):
             _plane(t, torch.uint8, f"ref{k}.{nm}", (H, W))
             planes.append(t)
+    arr = ctypes.c_void_p * 3
+    rr = arr(*[r[0].data_ptr() for r in refs])
+    rm = arr(*[r[1].data_ptr() for r in refs])
+    rk = arr(*[r[2].data_ptr() for r in refs])
+    return H, W, pitch, nref, rr, rm, rk, planes
+
+
+def reconstruct_frame(cur, cur_mask, refs=(), me: MEParams | None = None,
+                      fsr: FSRParams | None = None, out=None, out_u8=None, stage_events=None,
+                      workspace: Workspace | None = None, stream=None, first=None):
+    """One recursive frame (Fig. 1 order).  refs: sequence of
+    (recon uint8, meas uint8, mask uint8) device planes for lags 1..len(refs).
+    Returns (out float32 (H,W), out_u8 uint8 (H,W)).
+
+    first: None for the whole frame (rfsr_reconstruct_frame); otherwise the
+    frame's second part (rfsr_frame_finish): references of index < first,
+    projection and FSR, after `frame_motion(..., first)` ran the others into
+    the same workspace."""
+    me = me or MEParams()
+    fsr = fsr or FSRParams()
+    H, W, pitch, nref, rr, rm, rk, planes = _frame_args(cur, cur_mask, refs, "reconstruct_frame")
     dev = cur.device
     if out is None:
         out = torch.empty_strided((H, W), (pitch, 1), dtype=torch.float32, device=dev)
@@ -285,20 +311,39 @@ def reconstruct_frame(cur, cur_mask, refs=(), me: MEParams | None = None,
     planes += [_plane(out, torch.float32, "out", (H, W)), _plane(out_u8, torch.uint8, "out_u8", (H, W))]
     if any(p.stride(0) != pitch for p in planes):
         raise RfsrError("reconstruct_frame: all planes must share the row pitch")
-    arr = ctypes.c_void_p * 3
-    rr = arr(*[r[0].data_ptr() for r in refs])
-    rm = arr(*[r[1].data_ptr() for r in refs])
-    rk = arr(*[r[2].data_ptr() for r in refs])
     ev = None
     if stage_events is not None:
         ev = (ctypes.c_void_p * 4)(*[e.handle for e in stage_events])
     mc, fc = me.c(), fsr.c()
     ws = _ws(workspace, dev, workspace_bytes(H, W, nref, me, fsr))
-    st = lib().rfsr_reconstruct_frame(_ptr(cur), _ptr(cur_mask), nref, rr, rm, rk, H, W, pitch,
-                                      ctypes.byref(mc), ctypes.byref(fc), _ptr(out), _ptr(out_u8), ev,
-                                      _ptr(ws), ws.numel(), _stream(stream))
-    _check(st, "rfsr_reconstruct_frame")
+    if first is None:
+        st = lib().rfsr_reconstruct_frame(_ptr(cur), _ptr(cur_mask), nref, rr, rm, rk, H, W, pitch,
+                                          ctypes.byref(mc), ctypes.byref(fc), _ptr(out), _ptr(out_u8), ev,
+                                          _ptr(ws), ws.numel(), _stream(stream))
+        _check(st, "rfsr_reconstruct_frame")
+    else:
+        st = lib().rfsr_frame_finish(_ptr(cur), _ptr(cur_mask), nref, rr, rm, rk, H, W, pitch,
+                                     ctypes.byref(mc), ctypes.byref(fc), int(first), _ptr(out), _ptr(out_u8),
+                                     ev, _ptr(ws), ws.numel(), _stream(stream))
+        _check(st, "rfsr_frame_finish")
     return out, out_u8
+
+
+def frame_motion(cur, cur_mask, refs=(), me: MEParams | None = None, first: int = 1,
+                 workspace: Workspace | None = None, stream=None):
+    """First part of a frame split for pipelining (rfsr_frame_motion): the
+    window plane and the forward ME + check of the references of index
+    >= first (lags first+1..len(refs)) into `workspace`; complete the frame
+    with reconstruct_frame(..., first=first) on the same workspace."""
+    me = me or MEParams()
+    H, W, pitch, nref, rr, rm, rk, planes = _frame_args(cur, cur_mask, refs, "frame_motion")
+    if any(p.stride(0) != pitch for p in planes):
+        raise RfsrError("frame_motion: all planes must share the row pitch")
+    mc = me.c()
+    ws = _ws(workspace, cur.device, workspace_bytes(H, W, nref, me, None))
+    st = lib().rfsr_frame_motion(_ptr(cur), _ptr(cur_mask), nref, rr, rm, rk, H, W, pitch, ctypes.byref(mc),
+                                 int(first), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "rfsr_frame_motion")
 
 
 def quality_async(ref, test, border: int = 40, result=None, workspace: Workspace | None = None, stream=None):
@@ -339,6 +384,11 @@ class Event:
     def record(self, stream=None):
         _check(lib().rfsr_event_record(ctypes.c_void_p(self.handle), _stream(stream)), "rfsr_event_record")
 
+    def wait(self, stream=None):
+        """Make work enqueued on `stream` after this call wait for the
+        event's last record."""
+        _check(lib().rfsr_event_wait(ctypes.c_void_p(self.handle), _stream(stream)), "rfsr_event_wait")
+
     def elapsed_ms(self, end: "Event") -> float:
         ms = ctypes.c_float()
         _check(lib().rfsr_event_elapsed_ms(ctypes.c_void_p(self.handle), ctypes.c_void_p(end.handle),
@@ -357,10 +407,20 @@ class Sequence:
     """Causal recursion over a stream of frames: keeps the last three
     (reconstruction, measured frame, mask) planes resident on the device and
     reconstructs each new frame against them (Sec. 2.2, three previous
-    frames as in Sec. 4)."""
+    frames as in Sec. 4).
+
+    pipelined=True overlaps consecutive frames (same results): frame t's
+    references of lag >= 2 are final once frame t-2 is, so their motion
+    path (rfsr_frame_motion) runs on a side stream while frame t-1's FSR
+    runs (it starts once frame t-1's projection is done, so that it does
+    not compete with frame t-1's own motion path), and only the lag-1
+    reference, the projection and FSR (rfsr_frame_finish) wait for frame
+    t-1.  Two workspaces alternate between frames.  The inputs of push() must be complete on the device
+    when push() is called (pass `ready`, an event, if they are still being
+    produced)."""
 
     def __init__(self, H, W, me: MEParams | None = None, fsr: FSRParams | None = None,
-                 nref=3, device=None):
+                 nref=3, device=None, pipelined=False):
         self.H, self.W = H, W
         self.me = me or MEParams()
         self.fsr = fsr or FSRParams()
@@ -368,11 +428,58 @@ class Sequence:
         self.device = device or torch.device("cuda")
         self.ring = []
         self.workspace = Workspace(self.device)
+        self.pipelined = pipelined
+        if pipelined:
+            nbytes = workspace_bytes(H, W, nref, self.me, self.fsr)
+            self._ws = [Workspace(self.device), Workspace(self.device)]
+            for w in self._ws:
+                w.get(nbytes)
+            self._side = torch.cuda.Stream(device=self.device)   # default priority
+            self._done = [None, None]
+            self._stage = [[Event() for _ in range(4)] for _ in range(2)]
+            self._fsr_start = None   # stage event [2] of the last frame: its FSR is next
+            self._n = 0
 
-    def push(self, meas, mask, stage_events=None, stream=None):
+    def reset(self):
+        """Start a new recursion (the next frame has no references)."""
+        self.ring = []
+        if self.pipelined:
+            self._fsr_start = None
+
+    def push(self, meas, mask, stage_events=None, stream=None, out=None, out_u8=None, ready=None):
         refs = [(r[0], r[1], r[2]) for r in reversed(self.ring[-self.nref:])] if self.nref else []
-        out, out_u8 = reconstruct_frame(meas, mask, refs, self.me, self.fsr, stage_events=stage_events,
-                                        workspace=self.workspace, stream=stream)
+        if not self.pipelined:
+            out, out_u8 = reconstruct_frame(meas, mask, refs, self.me, self.fsr, out=out, out_u8=out_u8,
+                                            stage_events=stage_events, workspace=self.workspace, stream=stream)
+        else:
+            main = stream or torch.cuda.current_stream(self.device)
+            k = self._n % 2
+            ws = self._ws[k]
+            stage = stage_events if stage_events is not None else self._stage[k]
+            first = min(1, len(refs))
+            if len(refs) > first:
+                side = self._side
+                if self._done[k] is not None:   # frame t-2: its workspace and the lag >= 2 references
+                    side.wait_event(self._done[k])
+                if self._fsr_start is not None:   # frame t-1 has reached its FSR
+                    self._fsr_start.wait(side)
+                if ready is not None:
+                    side.wait_event(ready)
+                for t in [meas, mask] + [p for r in refs[first:] for p in r]:
+                    t.record_stream(side)
+                frame_motion(meas, mask, refs, self.me, first, workspace=ws, stream=side)
+                ev = torch.cuda.Event()
+                ev.record(side)
+                main.wait_event(ev)
+            elif ready is not None:
+                main.wait_event(ready)
+            out, out_u8 = reconstruct_frame(meas, mask, refs, self.me, self.fsr, out=out, out_u8=out_u8,
+                                            stage_events=stage, workspace=ws, stream=main, first=first)
+            done = torch.cuda.Event()
+            done.record(main)
+            self._done[k] = done
+            self._fsr_start = stage[2]
+            self._n += 1
         self.ring.append((out_u8, meas, mask))
         if len(self.ring) > self.nref:
             self.ring.pop(0)

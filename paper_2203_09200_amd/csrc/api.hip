@@ -14,7 +14,7 @@ using namespace rfsr;
 
 namespace {
 
-constexpr int32_t kVersion = 10400;   // 1.4.0
+constexpr int32_t kVersion = 10500;   // 1.5.0
 constexpr int kMaxBatch = 4096;
 
 rfsr_status from_hip(hipError_t e) { return e == hipSuccess ? RFSR_OK : RFSR_EDEVICE; }
@@ -105,8 +105,8 @@ struct Frame {
     int64_t pitch;
 };
 
-rfsr_status check_frame(const Frame& f) {
-    if (!f.cur || !f.cur_mask || !f.out) return RFSR_EINVAL;
+rfsr_status check_frame(const Frame& f, bool need_out = true) {
+    if (!f.cur || !f.cur_mask || (need_out && !f.out)) return RFSR_EINVAL;
     if (f.nref < 0 || f.nref > 3) return RFSR_EINVAL;
     for (int k = 0; k < f.nref; ++k)
         if (!f.ref_recon[k] || !f.ref_meas[k] || !f.ref_mask[k]) return RFSR_EINVAL;
@@ -143,7 +143,7 @@ void make_jobs(const Frame& f, uint8_t* base, bool windows, FrameJob& fj, RefJob
         j.mv_b = reinterpret_cast<int8_t*>(base + L.mv_b[k]);
         j.accept = base + L.acc[k];
         j.cost = reinterpret_cast<uint16_t*>(base + L.cost[k]);
-        j.nmap_w = k == 0 ? base + L.nmap : nullptr;   // n depends on the frame only
+        j.nmap_w = k == 0 ? base + L.nmap : nullptr;   // n depends on the frame only (see plan_batch)
         j.nmap = base + L.nmap;
         j.fm = reinterpret_cast<const uint2*>(base + L.fm);
         j.ma = reinterpret_cast<int8_t*>(base + L.ma[k]);
@@ -230,9 +230,22 @@ struct BatchLayout {
     }
 };
 
-// FNV-1a over the descriptors, the check and the workspace address: the
-// table image is valid exactly for this combination.
-unsigned long long batch_key(const rfsr_frame_desc* d, int n, int check, const void* ws) {
+// The share of a frame's work that one call runs: the motion path of
+// references [r0, r1) (clipped to the frame's), the window plane if
+// `windows`, and with `finish` the FSR tables, projection and FSR.  A batch
+// (and a whole frame) runs everything; a frame split for pipelining runs its
+// references of lag > first early (windows, no finish) and the rest with the
+// finish.
+struct Part {
+    int r0 = 0, r1 = 3;
+    bool windows = true;
+    bool finish = true;
+};
+
+// FNV-1a over the descriptors, the check, the workspace address and the
+// share of work: the table image is valid exactly for this combination.
+unsigned long long batch_key(const rfsr_frame_desc* d, int n, int check, const void* ws,
+                             const Part& part = Part()) {
     unsigned long long h = 1469598103934665603ull;
     auto mix = [&h](const void* p, size_t len) {
         const uint8_t* b = static_cast<const uint8_t*>(p);
@@ -242,9 +255,11 @@ unsigned long long batch_key(const rfsr_frame_desc* d, int n, int check, const v
         }
     };
     const uintptr_t addr = reinterpret_cast<uintptr_t>(ws);
+    const int pw[4] = {part.r0, part.r1, part.windows, part.finish};
     mix(&n, sizeof(n));
     mix(&check, sizeof(check));
     mix(&addr, sizeof(addr));
+    mix(pw, sizeof(pw));
     for (int i = 0; i < n; ++i) {
         // hash the fields, not the struct bytes (reserved / padding ignored)
         mix(&d[i].cur, sizeof(d[i].cur));
@@ -273,7 +288,7 @@ struct BatchPlan {
 };
 
 BatchPlan plan_batch(const rfsr_frame_desc* d, int n, const rfsr_me_params& me, uint8_t* ws,
-                     const BatchLayout& L) {
+                     const BatchLayout& L, const Part& part = Part()) {
     BatchPlan p;
     p.frames.resize(n);
     p.refs.reserve(L.nrefs);
@@ -287,9 +302,14 @@ BatchPlan plan_batch(const rfsr_frame_desc* d, int n, const rfsr_me_params& me, 
         fj.g_win = p.win;
         fj.g_blk = p.blocks;
         p.px_frames += px_groups(f.H, f.W);
-        p.win += windows ? win_groups(f.H, f.W) : 0;
+        p.win += windows && part.windows ? win_groups(f.H, f.W) : 0;
         p.blocks += (f.H / kBlock) * (f.W / kBlock);
-        for (int k = 0; k < f.nref; ++k) {
+        const int k0 = max(part.r0, 0);
+        for (int k = k0; k < min(part.r1, f.nref); ++k) {
+            // the n map depends on the frame only: the first reference a call
+            // runs writes it (a frame split for pipelining writes it twice,
+            // with the same values, the second time after the first call)
+            rj[k].nmap_w = k == k0 ? const_cast<uint8_t*>(rj[k].nmap) : nullptr;
             rj[k].g_tile = p.tiles;
             rj[k].g_px = p.px_refs;
             rj[k].g_frmc = p.frmc;
@@ -305,12 +325,12 @@ BatchPlan plan_batch(const rfsr_frame_desc* d, int n, const rfsr_me_params& me, 
 // Host image of a batch's job tables: header (with the batch key) |
 // FrameJob[n] | RefJob[total references].
 void write_image(const rfsr_frame_desc* frames, int n, const rfsr_me_params& me, uint8_t* ws,
-                 const BatchLayout& L, uint8_t* img) {
-    const BatchPlan p = plan_batch(frames, n, me, ws, L);
+                 const BatchLayout& L, uint8_t* img, const Part& part = Part()) {
+    const BatchPlan p = plan_batch(frames, n, me, ws, L, part);
     memset(img, 0, L.table_bytes);
     TableHeader hdr;
     memset(&hdr, 0, sizeof(hdr));
-    hdr.key = batch_key(frames, n, me.check, ws);
+    hdr.key = batch_key(frames, n, me.check, ws, part);
     hdr.n_frames = n;
     hdr.n_refs = (int)p.refs.size();
     memcpy(img, &hdr, sizeof(hdr));
@@ -337,10 +357,11 @@ __global__ __launch_bounds__(256) void write_table_kernel(FrameTableImage img, u
 // reference) pairs, projection, FSR; stage events around the stages.  With
 // `upload`, that image is first written to `img` (after the start event).
 hipError_t run_batch(const rfsr_frame_desc* frames, int n, const rfsr_me_params& me,
-                     const rfsr_fsr_params& fsr, const uint8_t* img, const FrameTableImage* upload,
-                     void* const* stage_events, uint8_t* ws, const BatchLayout& L, hipStream_t s) {
-    const BatchPlan p = plan_batch(frames, n, me, ws, L);   // grid sizes
-    const unsigned long long key = batch_key(frames, n, me.check, ws);
+                     const rfsr_fsr_params* fsr, const uint8_t* img, const FrameTableImage* upload,
+                     void* const* stage_events, uint8_t* ws, const BatchLayout& L, hipStream_t s,
+                     const Part& part = Part()) {
+    const BatchPlan p = plan_batch(frames, n, me, ws, L, part);   // grid sizes
+    const unsigned long long key = batch_key(frames, n, me.check, ws, part);
     const Jobs<FrameJob> jf = table<FrameJob>(img, kTableHeader, n, key);
     const Jobs<RefJob> jr = table<RefJob>(img, L.refs_offset, (int)p.refs.size(), key);
     FsrTables* tab = reinterpret_cast<FsrTables*>(ws);
@@ -354,17 +375,62 @@ hipError_t run_batch(const rfsr_frame_desc* frames, int n, const rfsr_me_params&
                            reinterpret_cast<uint32_t*>(const_cast<uint8_t*>(img)));
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = launch_fsr_tables(tab, fsr.rho, s);
+    if (e == hipSuccess && part.finish) e = launch_fsr_tables(tab, fsr->rho, s);
     if (e == hipSuccess && !p.refs.empty()) {
         e = launch_windows(jf, p.win, s);
         if (e == hipSuccess) e = launch_motion(jr, p.tiles, p.px_refs, p.frmc, me, nullptr, s);
     }
     record(1);
-    if (e == hipSuccess) e = launch_project(jf, p.px_frames, s);
+    if (e == hipSuccess && part.finish) e = launch_project(jf, p.px_frames, s);
     record(2);
-    if (e == hipSuccess) e = launch_fsr(jf, p.blocks, fsr, tab, s, p.frames.data());
+    if (e == hipSuccess && part.finish) e = launch_fsr(jf, p.blocks, *fsr, tab, s, p.frames.data());
     record(3);
     return e;
+}
+
+// One frame's share of work (`part`) as a batch of one: validation, then the
+// job-table image written into table slot `slot` after the frame's scratch
+// (in stream order, by a one-workgroup kernel), then the launch chain.
+rfsr_status frame_call(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
+                       const uint8_t* const* ref_recon, const uint8_t* const* ref_meas,
+                       const uint8_t* const* ref_mask, int32_t H, int32_t W, int64_t pitch,
+                       const rfsr_me_params* me, const rfsr_fsr_params* fsr, float* out, uint8_t* out_u8,
+                       void* const* stage_events, void* workspace, size_t ws_bytes, void* stream,
+                       const Part& part, int slot) {
+    if (nref < 0 || nref > 3) return RFSR_EINVAL;
+    if (nref > 0 && (!ref_recon || !ref_meas || !ref_mask)) return RFSR_EINVAL;
+    if (stage_events)
+        for (int k = 0; k < 4; ++k)
+            if (!stage_events[k]) return RFSR_EINVAL;
+    rfsr_frame_desc d;
+    memset(&d, 0, sizeof(d));
+    d.cur = cur;
+    d.cur_mask = cur_mask;
+    for (int k = 0; k < nref; ++k) {
+        d.ref_recon[k] = ref_recon[k];
+        d.ref_meas[k] = ref_meas[k];
+        d.ref_mask[k] = ref_mask[k];
+    }
+    d.out = out;
+    d.out_u8 = out_u8;
+    d.nref = nref;
+    d.H = H;
+    d.W = W;
+    d.pitch = pitch;
+    rfsr_status st = check_frame(to_frame(d), part.finish);
+    if (st != RFSR_OK) return st;
+    if ((st = check_me(me)) != RFSR_OK) return st;
+    if (part.finish && (st = check_fsr(fsr)) != RFSR_OK) return st;
+    const size_t scratch = single_ws(H, W, nref > 0 ? nref : 1);
+    if ((st = check_ws(workspace, ws_bytes, scratch + kFrameTable * (size_t)(slot + 1))) != RFSR_OK) return st;
+    if (!part.finish && part.r0 >= nref) return RFSR_OK;   // nothing to run early
+
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    const BatchLayout L(&d, 1);   // L.total <= scratch, L.table_bytes <= kFrameTable
+    FrameTableImage img;
+    write_image(&d, 1, *me, ws, L, reinterpret_cast<uint8_t*>(img.w), part);
+    return from_hip(run_batch(&d, 1, *me, fsr, ws + scratch + kFrameTable * (size_t)slot, &img, stage_events,
+                              ws, L, static_cast<hipStream_t>(stream), part));
 }
 
 }  // namespace
@@ -376,7 +442,7 @@ size_t rfsr_workspace_bytes(int32_t H, int32_t W, int32_t nref, const rfsr_me_pa
     if (check_shape(H, W, W) != RFSR_OK || nref < 0 || nref > 3) return 0;
     if (me && check_me(me) == RFSR_EINVAL) return 0;
     if (fsr && check_fsr(fsr) == RFSR_EINVAL) return 0;
-    return single_ws(H, W, nref > 0 ? nref : 1) + kFrameTable;
+    return single_ws(H, W, nref > 0 ? nref : 1) + 2 * kFrameTable;
 }
 
 rfsr_status rfsr_motion_check(const uint8_t* cur, const uint8_t* cur_mask, const uint8_t* ref_recon,
@@ -453,57 +519,39 @@ rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, 
                                    const rfsr_fsr_params* fsr, float* out, uint8_t* out_u8,
                                    void* const* stage_events, void* workspace, size_t ws_bytes,
                                    void* stream) {
-    if (nref < 0 || nref > 3) return RFSR_EINVAL;
-    if (nref > 0 && (!ref_recon || !ref_meas || !ref_mask)) return RFSR_EINVAL;
-    if (stage_events)
-        for (int k = 0; k < 4; ++k)
-            if (!stage_events[k]) return RFSR_EINVAL;
-    Frame f;
-    memset(&f, 0, sizeof(f));
-    f.cur = cur;
-    f.cur_mask = cur_mask;
-    for (int k = 0; k < nref; ++k) {
-        f.ref_recon[k] = ref_recon[k];
-        f.ref_meas[k] = ref_meas[k];
-        f.ref_mask[k] = ref_mask[k];
-    }
-    f.out = out;
-    f.out_u8 = out_u8;
-    f.nref = nref;
-    f.H = H;
-    f.W = W;
-    f.pitch = pitch;
-    rfsr_status st = check_frame(f);
-    if (st != RFSR_OK) return st;
-    if ((st = check_me(me)) != RFSR_OK) return st;
-    if ((st = check_fsr(fsr)) != RFSR_OK) return st;
-    const size_t scratch = single_ws(H, W, nref > 0 ? nref : 1);
-    if ((st = check_ws(workspace, ws_bytes, scratch + kFrameTable)) != RFSR_OK) return st;
+    return frame_call(cur, cur_mask, nref, ref_recon, ref_meas, ref_mask, H, W, pitch, me, fsr, out, out_u8,
+                      stage_events, workspace, ws_bytes, stream, Part(), 0);
+}
 
-    // A batch of one frame: its job tables (frame + references) go to the
-    // end of the workspace, written in stream order by a one-workgroup
-    // kernel, and every stage is one launch over all references.
-    rfsr_frame_desc d;
-    memset(&d, 0, sizeof(d));
-    d.cur = cur;
-    d.cur_mask = cur_mask;
-    for (int k = 0; k < nref; ++k) {
-        d.ref_recon[k] = ref_recon[k];
-        d.ref_meas[k] = ref_meas[k];
-        d.ref_mask[k] = ref_mask[k];
-    }
-    d.out = out;
-    d.out_u8 = out_u8;
-    d.nref = nref;
-    d.H = H;
-    d.W = W;
-    d.pitch = pitch;
-    uint8_t* ws = static_cast<uint8_t*>(workspace);
-    const BatchLayout L(&d, 1);   // L.total <= scratch, L.table_bytes <= kFrameTable
-    FrameTableImage img;
-    write_image(&d, 1, *me, ws, L, reinterpret_cast<uint8_t*>(img.w));
-    return from_hip(run_batch(&d, 1, *me, *fsr, ws + scratch, &img, stage_events, ws, L,
-                              static_cast<hipStream_t>(stream)));
+rfsr_status rfsr_frame_motion(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
+                              const uint8_t* const* ref_recon, const uint8_t* const* ref_meas,
+                              const uint8_t* const* ref_mask, int32_t H, int32_t W, int64_t pitch,
+                              const rfsr_me_params* me, int32_t first, void* workspace, size_t ws_bytes,
+                              void* stream) {
+    if (first < 0 || first > nref) return RFSR_EINVAL;
+    Part part;
+    part.r0 = first;
+    part.r1 = 3;
+    part.windows = true;
+    part.finish = false;
+    return frame_call(cur, cur_mask, nref, ref_recon, ref_meas, ref_mask, H, W, pitch, me, nullptr, nullptr,
+                      nullptr, nullptr, workspace, ws_bytes, stream, part, 1);
+}
+
+rfsr_status rfsr_frame_finish(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
+                              const uint8_t* const* ref_recon, const uint8_t* const* ref_meas,
+                              const uint8_t* const* ref_mask, int32_t H, int32_t W, int64_t pitch,
+                              const rfsr_me_params* me, const rfsr_fsr_params* fsr, int32_t first,
+                              float* out, uint8_t* out_u8, void* const* stage_events, void* workspace,
+                              size_t ws_bytes, void* stream) {
+    if (first < 0 || first > nref) return RFSR_EINVAL;
+    Part part;
+    part.r0 = 0;
+    part.r1 = first;
+    part.windows = first == nref;   // otherwise built by rfsr_frame_motion
+    part.finish = true;
+    return frame_call(cur, cur_mask, nref, ref_recon, ref_meas, ref_mask, H, W, pitch, me, fsr, out, out_u8,
+                      stage_events, workspace, ws_bytes, stream, part, 0);
 }
 
 size_t rfsr_batch_workspace_bytes(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
@@ -547,7 +595,7 @@ rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n, con
     const BatchLayout L(frames, n);
     if ((st = check_ws(workspace, ws_bytes, L.total)) != RFSR_OK) return st;
 
-    return from_hip(run_batch(frames, n, *me, *fsr, static_cast<const uint8_t*>(job_tables), nullptr,
+    return from_hip(run_batch(frames, n, *me, fsr, static_cast<const uint8_t*>(job_tables), nullptr,
                               stage_events, static_cast<uint8_t*>(workspace), L,
                               static_cast<hipStream_t>(stream)));
 }
@@ -589,6 +637,11 @@ rfsr_status rfsr_event_destroy(void* event) {
 rfsr_status rfsr_event_record(void* event, void* stream) {
     if (!event) return RFSR_EINVAL;
     return from_hip(hipEventRecord(static_cast<hipEvent_t>(event), static_cast<hipStream_t>(stream)));
+}
+
+rfsr_status rfsr_event_wait(void* event, void* stream) {
+    if (!event) return RFSR_EINVAL;
+    return from_hip(hipStreamWaitEvent(static_cast<hipStream_t>(stream), static_cast<hipEvent_t>(event), 0));
 }
 
 rfsr_status rfsr_event_elapsed_ms(void* start, void* stop, float* ms) {

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol(R):
     lib = R.lib()
     for n in declared_functions():
         assert hasattr(lib, n), n
-    assert lib.rfsr_version() == 10400
+    assert lib.rfsr_version() == 10500
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.rfsr_status_string(code).startswith(b"RFSR_")
 
@@ -113,6 +113,35 @@ def test_reconstruct_frame_rejects_bad_arguments(R):
                                       ctypes.byref(fsr), fake, None, ev, fake, 1 << 20, None) == -1
     assert lib.rfsr_reconstruct_frame(fake, fake, 0, None, None, None, 8, 8, 8, ctypes.byref(me),
                                       ctypes.byref(fsr), fake, None, None, fake, 64, None) == -3
+
+
+def test_frame_split_rejects_bad_arguments(R):
+    """rfsr_frame_motion / rfsr_frame_finish: `first` outside 0..nref, a null
+    output, a too small workspace; first == nref leaves nothing for the
+    early part, which returns OK without any device work."""
+    lib = R.lib()
+    P = ctypes.c_void_p
+    fake = P(4096)   # never dereferenced
+    me = R.MEParams().c()
+    fsr = R.FSRParams().c()
+    ok = (P * 3)(4096, 4096, 4096)
+    big = 1 << 20
+    for first, nref in ((-1, 2), (3, 2), (1, 0)):
+        assert lib.rfsr_frame_motion(fake, fake, nref, ok, ok, ok, 8, 8, 8, ctypes.byref(me), first,
+                                     fake, big, None) == -1, (first, nref)
+        assert lib.rfsr_frame_finish(fake, fake, nref, ok, ok, ok, 8, 8, 8, ctypes.byref(me), ctypes.byref(fsr),
+                                     first, fake, None, None, fake, big, None) == -1, (first, nref)
+    assert lib.rfsr_frame_finish(fake, fake, 2, ok, ok, ok, 8, 8, 8, ctypes.byref(me), ctypes.byref(fsr), 1,
+                                 None, None, None, fake, big, None) == -1
+    assert lib.rfsr_frame_motion(fake, fake, 2, ok, ok, ok, 6, 8, 8, ctypes.byref(me), 1, fake, big, None) == -2
+    assert lib.rfsr_frame_motion(fake, fake, 2, ok, ok, ok, 8, 8, 8, ctypes.byref(me), 1, fake, 16, None) == -3
+    assert lib.rfsr_frame_finish(fake, fake, 2, ok, ok, ok, 8, 8, 8, ctypes.byref(me), ctypes.byref(fsr), 1,
+                                 fake, None, None, fake, 16, None) == -3
+    # the early part needs the second table slot: the workspace of one slot is too small
+    one_slot = R.workspace_bytes(8, 8, 2) - 1024
+    assert lib.rfsr_frame_motion(fake, fake, 2, ok, ok, ok, 8, 8, 8, ctypes.byref(me), 1, fake, one_slot,
+                                 None) == -3
+    assert lib.rfsr_frame_motion(fake, fake, 2, ok, ok, ok, 8, 8, 8, ctypes.byref(me), 2, fake, big, None) == 0
 
 
 def test_binding_refuses_host_tensors(R):

@@ -104,3 +104,50 @@ def test_frame_ignores_unmeasured_values(check):
         outs.append([host(x) for x in (o, u, mv, acc, cost)])
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("check", ["nnc_frmc", "rmc", "rme"])
+def test_frame_split_equals_whole(check):
+    """rfsr_frame_motion(first) + rfsr_frame_finish(first) on one workspace
+    give bit-identical outputs to rfsr_reconstruct_frame for every split
+    point first = 0..3 (ragged 44x60 frame, three references)."""
+    R = need_gpu()
+    rng = np.random.default_rng(45)
+    H, W = 44, 60
+    frames, _ = synth.video_translate_edges(4, H, W, rng, max_step=3, n_edges=3)
+    masks = synth.mask_sequence("dynamic", 4, H, W, rng)
+    meas = synth.measured(frames, masks)
+    refs = [(dev(frames[2 - k]), dev(meas[2 - k]), dev(masks[2 - k])) for k in range(3)]
+    cur, mask = dev(meas[3]), dev(masks[3])
+    me, fsr = R.MEParams(search=6, check=check), R.FSRParams(iters=30)
+    o, u = R.reconstruct_frame(cur, mask, refs, me, fsr)
+    whole = (host(o), host(u))
+    nbytes = R.workspace_bytes(H, W, 3, me, fsr)
+    for first in range(4):
+        ws = R.Workspace()
+        ws.get(nbytes).random_(0, 256)   # no state from an earlier call can help
+        R.frame_motion(cur, mask, refs, me, first, workspace=ws)
+        o2, u2 = R.reconstruct_frame(cur, mask, refs, me, fsr, workspace=ws, first=first)
+        assert np.array_equal(host(o2), whole[0]) and np.array_equal(host(u2), whole[1]), first
+
+
+@pytest.mark.parametrize("H,W,T", [(64, 80, 7), (1080, 1920, 5)])
+def test_pipelined_sequence_equals_plain(H, W, T):
+    """The pipelined recursion (early motion path of the lag >= 2 references
+    on a side stream, overlapping the previous frame's FSR) reproduces the
+    plain recursion bit for bit, frame by frame."""
+    R = need_gpu()
+    frames, masks = synth.workload_c2(n=T, h=H, w=W, seed=synth.seed_for(7))
+    meas = synth.measured(frames, masks)
+    d_meas = [dev(x) for x in meas]
+    d_mask = [dev(x) for x in masks]
+    torch.cuda.synchronize()
+    me, fsr = R.MEParams(search=9, check="nnc_frmc"), R.FSRParams(iters=100)
+    res = []
+    for pipelined in (False, True):
+        seq = R.Sequence(H, W, me, fsr, pipelined=pipelined)
+        outs = [seq.push(d_meas[t], d_mask[t]) for t in range(T)]
+        torch.cuda.synchronize()
+        res.append([(host(o), host(u)) for o, u in outs])
+    for t in range(T):
+        assert np.array_equal(res[0][t][0], res[1][t][0]) and np.array_equal(res[0][t][1], res[1][t][1]), t
