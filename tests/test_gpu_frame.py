@@ -131,8 +131,9 @@ def test_frame_split_equals_whole(check):
         assert np.array_equal(host(o2), whole[0]) and np.array_equal(host(u2), whole[1]), first
 
 
-@pytest.mark.parametrize("H,W,T", [(64, 80, 7), (1080, 1920, 5)])
-def test_pipelined_sequence_equals_plain(H, W, T):
+@pytest.mark.parametrize("H,W,T,check", [(64, 80, 7, "nnc_frmc"), (64, 80, 6, "rme"), (64, 80, 6, "rmc"),
+                                         (64, 80, 6, "frmc"), (64, 80, 6, "none"), (1080, 1920, 5, "nnc_frmc")])
+def test_pipelined_sequence_equals_plain(H, W, T, check):
     """The pipelined recursion (early motion path of the lag >= 2 references
     on a side stream, overlapping the previous frame's FSR) reproduces the
     plain recursion bit for bit, frame by frame."""
@@ -142,7 +143,7 @@ def test_pipelined_sequence_equals_plain(H, W, T):
     d_meas = [dev(x) for x in meas]
     d_mask = [dev(x) for x in masks]
     torch.cuda.synchronize()
-    me, fsr = R.MEParams(search=9, check="nnc_frmc"), R.FSRParams(iters=100)
+    me, fsr = R.MEParams(search=9, check=check), R.FSRParams(iters=100)
     res = []
     for pipelined in (False, True):
         seq = R.Sequence(H, W, me, fsr, pipelined=pipelined)
