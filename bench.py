@@ -106,10 +106,13 @@ def cpu_baseline(frames, masks, me_o, fsr_o, crop=128):
 def run_multistream(a, dev):
     """48 streams of uneven size (16 x 352x288, 16 x 1280x720, 12 x 1920x1080,
     4 x 3840x2160; even streams fixed mask, odd dynamic), 8 frames each,
-    cycled.  One step = one time step of every stream as ONE batch
-    (rfsr_reconstruct_batch, replayed from a captured graph once every stream
-    has three references).  Inputs are resident in HBM; the per-step input
-    copies into the streams' ring slots are inside the timed region."""
+    cycled.  One step = one time step of every stream as ONE batch; by
+    default consecutive steps are pipelined (the lag-2/3 motion path of every
+    stream beside the previous step's FSR, rfsr_reconstruct_batch_part);
+    --no-pipeline: whole steps (rfsr_reconstruct_batch), replayed from a
+    captured graph once every stream has three references.  Inputs are
+    resident in HBM; the per-step input copies into the streams' ring slots
+    are inside the timed region."""
     import numpy as np
     import torch
     import synth
@@ -127,7 +130,8 @@ def run_multistream(a, dev):
     fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs, concealed_weight=a.concealed)
     px_step = sum(h * w for h, w in sizes)
 
-    ss = R.StreamSet(sizes, me, fsr, graphs=not a.no_graphs, device=dev)
+    pipelined = not a.no_pipeline
+    ss = R.StreamSet(sizes, me, fsr, graphs=not a.no_graphs, device=dev, pipelined=pipelined)
     warm = max(a.warmup, 0) * T + 4      # every ring phase captured before timing
     for t in range(warm):
         ss.step([m[t % T] for m in meas], [m[t % T] for m in masks])
@@ -179,9 +183,11 @@ def run_multistream(a, dev):
         "config": {"workload": f"48 streams (16x352x288, 16x1280x720, 12x1920x1080, 4x3840x2160), "
                                f"{T} frames cycled, even streams fixed mask / odd dynamic, D-FSR + "
                                f"{a.check.upper().replace('_', '+')}, R={a.search}, K={a.iters}, 3 references, "
-                               f"one batch per time step" + ("" if a.no_graphs else ", graph replay")
+                               f"one batch per time step" + (", pipelined time steps" if pipelined else
+                                                             "" if a.no_graphs else ", graph replay")
                                + (f", concealed weighting {a.concealed}" if a.concealed else ""),
-                   "streams": len(sizes), "hr_px_per_step": px_step, "parallelism": "single GPU"},
+                   "streams": len(sizes), "hr_px_per_step": px_step, "parallelism": "single GPU",
+                   "pipelined": pipelined},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3)},
         "psnr_db": round(psnr_mean, 3),
         "plain": plain,
@@ -203,7 +209,8 @@ def main(argv=None):
     ap.add_argument("--check", default="nnc_frmc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pipeline", action="store_true",
-                    help="c2: no overlap of consecutive frames (each frame's motion path after the previous frame)")
+                    help="no overlap of consecutive frames / time steps (each frame's motion path after the "
+                         "previous frame)")
     ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
                     help="c2: the metric's 1080p recursion (default); c4: 48 streams of uneven "
                          "size advanced one time step per batch")

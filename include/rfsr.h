@@ -318,6 +318,31 @@ rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n,
                                    const void* job_tables, void* const* stage_events,
                                    void* workspace, size_t ws_bytes, void* stream);
 
+/* A batch split like rfsr_frame_motion / rfsr_frame_finish, for pipelining
+ * consecutive time steps of the same streams (results unchanged):
+ *   RFSR_PART_MOTION  window planes and motion path of every frame's
+ *                     references first..nref-1 (frames with nref <= first:
+ *                     nothing); `fsr` may be NULL;
+ *   RFSR_PART_FINISH  references 0..first-1, the window planes of frames
+ *                     without early references, projections and FSR; the
+ *                     MOTION part with the same frames, `first` and workspace
+ *                     must be ordered before it by the caller;
+ *   RFSR_PART_ALL     whole frames (rfsr_reconstruct_batch; `first` ignored).
+ * Each part reads its own job-table image, written by
+ * rfsr_batch_write_tables_part with the same part and first (at most
+ * rfsr_batch_table_bytes bytes).  0 <= first <= 3.
+ * Errors: as rfsr_batch_write_tables / rfsr_reconstruct_batch; RFSR_EINVAL
+ * for an unknown part or first outside 0..3. */
+typedef enum { RFSR_PART_ALL = 0, RFSR_PART_MOTION = 1, RFSR_PART_FINISH = 2 } rfsr_part;
+rfsr_status rfsr_batch_write_tables_part(const rfsr_frame_desc* frames, int32_t n,
+                                         const rfsr_me_params* me, int32_t part, int32_t first,
+                                         const void* workspace, void* image, size_t image_bytes);
+rfsr_status rfsr_reconstruct_batch_part(const rfsr_frame_desc* frames, int32_t n,
+                                        const rfsr_me_params* me, const rfsr_fsr_params* fsr,
+                                        int32_t part, int32_t first, const void* job_tables,
+                                        void* const* stage_events, void* workspace, size_t ws_bytes,
+                                        void* stream);
+
 /* ------------------------------------------------------------- quality ---
  * Reconstruction quality as evaluated in Sec. 4: PSNR and mean SSIM of a
  * reconstruction against the ground truth with a border of `border` pixels

@@ -127,6 +127,15 @@ def lib():
     L.rfsr_batch_write_tables.restype = _STATUS
     L.rfsr_batch_write_tables.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32,
                                           ctypes.POINTER(_MEParams), _P, _P, ctypes.c_size_t]
+    L.rfsr_batch_write_tables_part.restype = _STATUS
+    L.rfsr_batch_write_tables_part.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32,
+                                               ctypes.POINTER(_MEParams), ctypes.c_int32, ctypes.c_int32, _P,
+                                               _P, ctypes.c_size_t]
+    L.rfsr_reconstruct_batch_part.restype = _STATUS
+    L.rfsr_reconstruct_batch_part.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32,
+                                              ctypes.POINTER(_MEParams), ctypes.POINTER(_FSRParams),
+                                              ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P), _P,
+                                              ctypes.c_size_t, _P]
     L.rfsr_reconstruct_batch.restype = _STATUS
     L.rfsr_reconstruct_batch.argtypes = [ctypes.POINTER(FrameDesc), ctypes.c_int32,
                                          ctypes.POINTER(_MEParams), ctypes.POINTER(_FSRParams), _P,
@@ -540,12 +549,20 @@ class Batch:
     stream: if given, the job tables are uploaded asynchronously on it (from
     pinned memory) and the host does not wait; run the batch on the same
     stream.  Otherwise the upload completes before the constructor returns.
+    part / first: "all" (whole frames), or one part of the frames split at
+    reference index `first` for pipelining ("motion": the motion path of
+    references first.., "finish": the rest; rfsr_reconstruct_batch_part).
     """
 
+    PARTS = {"all": 0, "motion": 1, "finish": 2}
+
     def __init__(self, frames, me: MEParams | None = None, fsr: FSRParams | None = None,
-                 workspace: torch.Tensor | None = None, stream=None):
+                 workspace: torch.Tensor | None = None, stream=None, part: str = "all", first: int = 0):
         if not frames:
             raise RfsrError("Batch: no frames")
+        if part not in self.PARTS:
+            raise RfsrError(f"Batch: part must be one of {sorted(self.PARTS)}")
+        self.part, self.first = self.PARTS[part], int(first)
         self.frames = list(frames)
         self.me = me or MEParams()
         self.fsr = fsr or FSRParams()
@@ -564,8 +581,8 @@ class Batch:
         self.workspace = workspace
         tb = int(L.rfsr_batch_table_bytes(self.descs, self.n))
         image = torch.empty(tb, dtype=torch.uint8, pin_memory=True)
-        _check(L.rfsr_batch_write_tables(self.descs, self.n, ctypes.byref(self._mc), _ptr(workspace),
-                                         _ptr(image), tb), "rfsr_batch_write_tables")
+        _check(L.rfsr_batch_write_tables_part(self.descs, self.n, ctypes.byref(self._mc), self.part, self.first,
+                                              _ptr(workspace), _ptr(image), tb), "rfsr_batch_write_tables_part")
         if stream is None:
             self.tables = torch.empty(tb, dtype=torch.uint8, device=self.device)
             self.tables.copy_(image)
@@ -591,10 +608,10 @@ class Batch:
         ev = None
         if stage_events is not None:
             ev = (ctypes.c_void_p * 4)(*[e.handle for e in stage_events])
-        st = lib().rfsr_reconstruct_batch(self.descs, self.n, ctypes.byref(self._mc), ctypes.byref(self._fc),
-                                          _ptr(self.tables), ev, _ptr(self.workspace), self.workspace.numel(),
-                                          _stream(stream))
-        _check(st, "rfsr_reconstruct_batch")
+        st = lib().rfsr_reconstruct_batch_part(self.descs, self.n, ctypes.byref(self._mc), ctypes.byref(self._fc),
+                                               self.part, self.first, _ptr(self.tables), ev, _ptr(self.workspace),
+                                               self.workspace.numel(), _stream(stream))
+        _check(st, "rfsr_reconstruct_batch_part")
         return [(f.out, f.out_u8) for f in self.frames]
 
     def capture(self):
@@ -616,19 +633,26 @@ class StreamSet:
     time step t writes slot t mod 4 and references slots t-1..t-3.  The
     buffer pattern repeats every four steps, so from t = 3 on the chain of
     each phase is captured once in a graph and replayed (graphs=True).
+
+    pipelined=True overlaps consecutive time steps as Sequence does (same
+    results; eager launches, no graphs): the motion path of every stream's
+    lag-2/3 references runs on a side stream beside the previous step's
+    FSR, with two workspaces alternating between steps.  The inputs of
+    step() must be complete on the device when step() is called.
     """
 
     SLOTS = 4
 
     def __init__(self, sizes, me: MEParams | None = None, fsr: FSRParams | None = None,
-                 nref: int = 3, graphs: bool = True, device=None):
+                 nref: int = 3, graphs: bool = True, device=None, pipelined: bool = False):
         if not 0 <= nref <= 3:
             raise RfsrError("nref must be in 0..3")
         self.sizes = [tuple(map(int, s)) for s in sizes]
         self.me = me or MEParams()
         self.fsr = fsr or FSRParams()
         self.nref = nref
-        self.graphs = graphs
+        self.pipelined = pipelined
+        self.graphs = graphs and not pipelined
         self.device = device or torch.device("cuda")
         dev = self.device
         mk = lambda H, W, dt: [torch.empty((H, W), dtype=dt, device=dev) for _ in range(self.SLOTS)]
@@ -639,10 +663,17 @@ class StreamSet:
         self.t = 0
         self._batches = {}
         self._graphs = {}
-        # one workspace for every phase (phases never overlap)
+        # one workspace for every phase (phases never overlap); pipelined:
+        # two, alternating between time steps (slot parity)
         need = max(Batch.workspace_bytes(self._frames(slot, self.nref), self.me, self.fsr)
                    for slot in range(self.SLOTS))
         self.workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        if pipelined:
+            self._wss = [self.workspace, torch.empty(need, dtype=torch.uint8, device=dev)]
+            self._side = torch.cuda.Stream(device=dev)   # default priority
+            self._done = [None, None]
+            self._stage = [[Event() for _ in range(4)] for _ in range(2)]
+            self._fsr_start = None
 
     def _frames(self, slot, nref):
         fr = []
@@ -662,6 +693,8 @@ class StreamSet:
             raise RfsrError("StreamSet.step: one frame and mask per stream")
         slot = self.t % self.SLOTS
         nref = min(self.t, self.nref)
+        if self.pipelined:
+            return self._step_pipelined(meas, masks, slot, nref, stage_events)
         for s in range(len(self.sizes)):
             self.meas[s][slot].copy_(meas[s], non_blocking=True)
             self.mask[s][slot].copy_(masks[s], non_blocking=True)
@@ -676,5 +709,52 @@ class StreamSet:
             g.replay()
         else:
             b.run(stage_events=stage_events)
+        self.t += 1
+        return [(self.out[s][slot], self.out_u8[s][slot]) for s in range(len(self.sizes))]
+
+    def _batch(self, slot, nref, part, first):
+        key = (slot, nref, part)
+        b = self._batches.get(key)
+        if b is None:
+            b = self._batches[key] = Batch(self._frames(slot, nref), self.me, self.fsr, self._wss[slot % 2],
+                                           part=part, first=first)
+        return b
+
+    def _step_pipelined(self, meas, masks, slot, nref, stage_events):
+        main = torch.cuda.current_stream(self.device)
+        k = slot % 2
+        stage = stage_events if stage_events is not None else self._stage[k]
+        first = min(1, nref)
+
+        def copy_inputs():
+            for s in range(len(self.sizes)):
+                self.meas[s][slot].copy_(meas[s], non_blocking=True)
+                self.mask[s][slot].copy_(masks[s], non_blocking=True)
+
+        if nref > first:
+            side = self._side
+            if self._done[k] is not None:   # step t-2: its workspace, the lag >= 2 references, slot t-4
+                side.wait_event(self._done[k])
+            if self._fsr_start is not None:   # step t-1 has reached its FSR
+                self._fsr_start.wait(side)
+            for t in list(meas) + list(masks):
+                t.record_stream(side)
+            with torch.cuda.stream(side):
+                copy_inputs()
+            self._batch(slot, nref, "motion", first).run(stream=side)
+            ev = torch.cuda.Event()
+            ev.record(side)
+            main.wait_event(ev)
+            fin = self._batch(slot, nref, "finish", first)
+        else:
+            if self._done[k] is not None:
+                main.wait_event(self._done[k])
+            copy_inputs()
+            fin = self._batch(slot, nref, "all", 0)
+        fin.run(stage_events=stage, stream=main)
+        done = torch.cuda.Event()
+        done.record(main)
+        self._done[k] = done
+        self._fsr_start = stage[2]
         self.t += 1
         return [(self.out[s][slot], self.out_u8[s][slot]) for s in range(len(self.sizes))]

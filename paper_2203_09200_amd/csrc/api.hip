@@ -230,16 +230,36 @@ struct BatchLayout {
     }
 };
 
-// The share of a frame's work that one call runs: the motion path of
-// references [r0, r1) (clipped to the frame's), the window plane if
-// `windows`, and with `finish` the FSR tables, projection and FSR.  A batch
-// (and a whole frame) runs everything; a frame split for pipelining runs its
-// references of lag > first early (windows, no finish) and the rest with the
-// finish.
+// The share of the work that one call runs.  Whole frames (`all`): every
+// reference, window planes, FSR tables, projection and FSR.  A frame split
+// for pipelining at reference index `first`: the early part runs the motion
+// path of references first..nref-1 and the window planes of the frames that
+// have such references; the finish runs references 0..first-1, the window
+// planes of the frames without early references, the tables, projection
+// and FSR.
 struct Part {
-    int r0 = 0, r1 = 3;
-    bool windows = true;
-    bool finish = true;
+    enum Kind { ALL = 0, MOTION = 1, FINISH = 2 };
+    int kind = ALL;
+    int first = 0;
+    bool finish() const { return kind != MOTION; }
+    int r0() const { return kind == MOTION ? first : 0; }
+    int r1(int nref) const { return kind == FINISH ? min(first, nref) : nref; }
+    // window planes of a frame with nref references (if the check needs them)
+    bool windows(int nref) const {
+        return kind == ALL || (kind == MOTION ? nref > first : nref <= first);
+    }
+    static Part motion(int first) {
+        Part p;
+        p.kind = MOTION;
+        p.first = first;
+        return p;
+    }
+    static Part finish_from(int first) {
+        Part p;
+        p.kind = FINISH;
+        p.first = first;
+        return p;
+    }
 };
 
 // FNV-1a over the descriptors, the check, the workspace address and the
@@ -255,7 +275,7 @@ unsigned long long batch_key(const rfsr_frame_desc* d, int n, int check, const v
         }
     };
     const uintptr_t addr = reinterpret_cast<uintptr_t>(ws);
-    const int pw[4] = {part.r0, part.r1, part.windows, part.finish};
+    const int pw[2] = {part.kind, part.first};
     mix(&n, sizeof(n));
     mix(&check, sizeof(check));
     mix(&addr, sizeof(addr));
@@ -302,10 +322,10 @@ BatchPlan plan_batch(const rfsr_frame_desc* d, int n, const rfsr_me_params& me, 
         fj.g_win = p.win;
         fj.g_blk = p.blocks;
         p.px_frames += px_groups(f.H, f.W);
-        p.win += windows && part.windows ? win_groups(f.H, f.W) : 0;
+        p.win += windows && part.windows(f.nref) ? win_groups(f.H, f.W) : 0;
         p.blocks += (f.H / kBlock) * (f.W / kBlock);
-        const int k0 = max(part.r0, 0);
-        for (int k = k0; k < min(part.r1, f.nref); ++k) {
+        const int k0 = part.r0();
+        for (int k = k0; k < part.r1(f.nref); ++k) {
             // the n map depends on the frame only: the first reference a call
             // runs writes it (a frame split for pipelining writes it twice,
             // with the same values, the second time after the first call)
@@ -375,15 +395,15 @@ hipError_t run_batch(const rfsr_frame_desc* frames, int n, const rfsr_me_params&
                            reinterpret_cast<uint32_t*>(const_cast<uint8_t*>(img)));
         e = hipGetLastError();
     }
-    if (e == hipSuccess && part.finish) e = launch_fsr_tables(tab, fsr->rho, s);
+    if (e == hipSuccess && part.finish()) e = launch_fsr_tables(tab, fsr->rho, s);
     if (e == hipSuccess && !p.refs.empty()) {
         e = launch_windows(jf, p.win, s);
         if (e == hipSuccess) e = launch_motion(jr, p.tiles, p.px_refs, p.frmc, me, nullptr, s);
     }
     record(1);
-    if (e == hipSuccess && part.finish) e = launch_project(jf, p.px_frames, s);
+    if (e == hipSuccess && part.finish()) e = launch_project(jf, p.px_frames, s);
     record(2);
-    if (e == hipSuccess && part.finish) e = launch_fsr(jf, p.blocks, *fsr, tab, s, p.frames.data());
+    if (e == hipSuccess && part.finish()) e = launch_fsr(jf, p.blocks, *fsr, tab, s, p.frames.data());
     record(3);
     return e;
 }
@@ -417,13 +437,13 @@ rfsr_status frame_call(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref
     d.H = H;
     d.W = W;
     d.pitch = pitch;
-    rfsr_status st = check_frame(to_frame(d), part.finish);
+    rfsr_status st = check_frame(to_frame(d), part.finish());
     if (st != RFSR_OK) return st;
     if ((st = check_me(me)) != RFSR_OK) return st;
-    if (part.finish && (st = check_fsr(fsr)) != RFSR_OK) return st;
+    if (part.finish() && (st = check_fsr(fsr)) != RFSR_OK) return st;
     const size_t scratch = single_ws(H, W, nref > 0 ? nref : 1);
     if ((st = check_ws(workspace, ws_bytes, scratch + kFrameTable * (size_t)(slot + 1))) != RFSR_OK) return st;
-    if (!part.finish && part.r0 >= nref) return RFSR_OK;   // nothing to run early
+    if (!part.finish() && part.first >= nref) return RFSR_OK;   // nothing to run early
 
     uint8_t* ws = static_cast<uint8_t*>(workspace);
     const BatchLayout L(&d, 1);   // L.total <= scratch, L.table_bytes <= kFrameTable
@@ -529,13 +549,8 @@ rfsr_status rfsr_frame_motion(const uint8_t* cur, const uint8_t* cur_mask, int32
                               const rfsr_me_params* me, int32_t first, void* workspace, size_t ws_bytes,
                               void* stream) {
     if (first < 0 || first > nref) return RFSR_EINVAL;
-    Part part;
-    part.r0 = first;
-    part.r1 = 3;
-    part.windows = true;
-    part.finish = false;
     return frame_call(cur, cur_mask, nref, ref_recon, ref_meas, ref_mask, H, W, pitch, me, nullptr, nullptr,
-                      nullptr, nullptr, workspace, ws_bytes, stream, part, 1);
+                      nullptr, nullptr, workspace, ws_bytes, stream, Part::motion(first), 1);
 }
 
 rfsr_status rfsr_frame_finish(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
@@ -545,13 +560,8 @@ rfsr_status rfsr_frame_finish(const uint8_t* cur, const uint8_t* cur_mask, int32
                               float* out, uint8_t* out_u8, void* const* stage_events, void* workspace,
                               size_t ws_bytes, void* stream) {
     if (first < 0 || first > nref) return RFSR_EINVAL;
-    Part part;
-    part.r0 = 0;
-    part.r1 = first;
-    part.windows = first == nref;   // otherwise built by rfsr_frame_motion
-    part.finish = true;
     return frame_call(cur, cur_mask, nref, ref_recon, ref_meas, ref_mask, H, W, pitch, me, fsr, out, out_u8,
-                      stage_events, workspace, ws_bytes, stream, part, 0);
+                      stage_events, workspace, ws_bytes, stream, Part::finish_from(first), 0);
 }
 
 size_t rfsr_batch_workspace_bytes(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
@@ -567,37 +577,58 @@ size_t rfsr_batch_table_bytes(const rfsr_frame_desc* frames, int32_t n) {
     return BatchLayout(frames, n).table_bytes;
 }
 
-rfsr_status rfsr_batch_write_tables(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
-                                    const void* workspace, void* image, size_t image_bytes) {
+rfsr_status rfsr_batch_write_tables_part(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
+                                         int32_t part, int32_t first, const void* workspace, void* image,
+                                         size_t image_bytes) {
     rfsr_status st = check_batch(frames, n);
     if (st != RFSR_OK) return st;
     if ((st = check_me(me)) != RFSR_OK) return st;
+    if (part < RFSR_PART_ALL || part > RFSR_PART_FINISH || first < 0 || first > 3) return RFSR_EINVAL;
     if (!workspace || ((uintptr_t)workspace & 255u) != 0) return RFSR_EWORKSPACE;
     const BatchLayout L(frames, n);
     if (!image || image_bytes < L.table_bytes) return RFSR_EINVAL;
+    Part pt;
+    pt.kind = part;
+    pt.first = part == RFSR_PART_ALL ? 0 : first;
     write_image(frames, n, *me, static_cast<uint8_t*>(const_cast<void*>(workspace)), L,
-                static_cast<uint8_t*>(image));
+                static_cast<uint8_t*>(image), pt);
     return RFSR_OK;
 }
 
-rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
-                                   const rfsr_fsr_params* fsr, const void* job_tables,
-                                   void* const* stage_events, void* workspace, size_t ws_bytes,
-                                   void* stream) {
+rfsr_status rfsr_batch_write_tables(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
+                                    const void* workspace, void* image, size_t image_bytes) {
+    return rfsr_batch_write_tables_part(frames, n, me, RFSR_PART_ALL, 0, workspace, image, image_bytes);
+}
+
+rfsr_status rfsr_reconstruct_batch_part(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
+                                        const rfsr_fsr_params* fsr, int32_t part, int32_t first,
+                                        const void* job_tables, void* const* stage_events, void* workspace,
+                                        size_t ws_bytes, void* stream) {
     rfsr_status st = check_batch(frames, n);
     if (st != RFSR_OK) return st;
     if ((st = check_me(me)) != RFSR_OK) return st;
-    if ((st = check_fsr(fsr)) != RFSR_OK) return st;
+    if (part < RFSR_PART_ALL || part > RFSR_PART_FINISH || first < 0 || first > 3) return RFSR_EINVAL;
+    if (part != RFSR_PART_MOTION && (st = check_fsr(fsr)) != RFSR_OK) return st;
     if (!job_tables || ((uintptr_t)job_tables & 255u) != 0) return RFSR_EINVAL;
     if (stage_events)
         for (int k = 0; k < 4; ++k)
             if (!stage_events[k]) return RFSR_EINVAL;
     const BatchLayout L(frames, n);
     if ((st = check_ws(workspace, ws_bytes, L.total)) != RFSR_OK) return st;
-
+    Part pt;
+    pt.kind = part;
+    pt.first = part == RFSR_PART_ALL ? 0 : first;
     return from_hip(run_batch(frames, n, *me, fsr, static_cast<const uint8_t*>(job_tables), nullptr,
                               stage_events, static_cast<uint8_t*>(workspace), L,
-                              static_cast<hipStream_t>(stream)));
+                              static_cast<hipStream_t>(stream), pt));
+}
+
+rfsr_status rfsr_reconstruct_batch(const rfsr_frame_desc* frames, int32_t n, const rfsr_me_params* me,
+                                   const rfsr_fsr_params* fsr, const void* job_tables,
+                                   void* const* stage_events, void* workspace, size_t ws_bytes,
+                                   void* stream) {
+    return rfsr_reconstruct_batch_part(frames, n, me, fsr, RFSR_PART_ALL, 0, job_tables, stage_events,
+                                       workspace, ws_bytes, stream);
 }
 
 size_t rfsr_quality_workspace_bytes(int32_t H, int32_t W, int32_t border) {

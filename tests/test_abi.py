@@ -4,6 +4,7 @@ device (no compute calls here)."""
 import ctypes
 import os
 import re
+import struct
 
 import pytest
 
@@ -196,7 +197,6 @@ def test_batch_tables_are_keyed_to_their_descriptors(R):
     """The job-table image is built on the host: its header counts the jobs and
     carries a key that changes with any descriptor, the check or the
     workspace address."""
-    import struct
     lib = R.lib()
     me = R.MEParams().c()
     shapes, nrefs = [(64, 64), (96, 128)], [3, 1]
@@ -224,6 +224,39 @@ def test_batch_tables_are_keyed_to_their_descriptors(R):
     # errors: image too small, misaligned workspace
     assert lib.rfsr_batch_write_tables(ds, 2, ctypes.byref(me), ctypes.c_void_p(1 << 30), img, tb - 1) == -1
     assert lib.rfsr_batch_write_tables(ds, 2, ctypes.byref(me), ctypes.c_void_p((1 << 30) + 8), img, tb) == -3
+
+
+def test_batch_part_tables(R):
+    """Job-table images of a batch split at reference index `first`: the
+    early part holds the references >= first of every frame, the finish the
+    others, each under its own key; unknown parts and first outside 0..3 are
+    rejected."""
+    lib = R.lib()
+    me = R.MEParams().c()
+    fsr = R.FSRParams().c()
+    shapes, nrefs = [(64, 64), (96, 128), (32, 32)], [3, 1, 2]
+    ds = _descs(R, shapes, nrefs)
+    tb = lib.rfsr_batch_table_bytes(ds, 3)
+    ws = ctypes.c_void_p(1 << 30)
+
+    def header(part, first):
+        img = ctypes.create_string_buffer(tb)
+        assert lib.rfsr_batch_write_tables_part(ds, 3, ctypes.byref(me), part, first, ws, img, tb) == 0
+        return struct.unpack_from("<Qii", img.raw, 0)
+
+    k_all, nf, nr = header(0, 0)
+    assert (nf, nr) == (3, 6)
+    k_mot, _, nr_mot = header(1, 1)
+    k_fin, _, nr_fin = header(2, 1)
+    assert (nr_mot, nr_fin) == (2 + 0 + 1, 1 + 1 + 1)
+    assert len({k_all, k_mot, k_fin}) == 3
+    assert header(0, 2)[0] == k_all          # `first` is ignored for whole frames
+    assert header(1, 0)[2] == 6 and header(2, 0)[2] == 0 and header(1, 3)[2] == 0
+    img = ctypes.create_string_buffer(tb)
+    for part, first in ((3, 1), (-1, 1), (1, -1), (2, 4)):
+        assert lib.rfsr_batch_write_tables_part(ds, 3, ctypes.byref(me), part, first, ws, img, tb) == -1
+        assert lib.rfsr_reconstruct_batch_part(ds, 3, ctypes.byref(me), ctypes.byref(fsr), part, first, ws, None,
+                                               ws, 1 << 40, None) == -1
 
 
 def test_reconstruct_batch_rejects_bad_arguments(R):

@@ -86,6 +86,39 @@ def test_stream_set_with_graphs_equals_sequences():
     assert len(ss._graphs) == 4   # one per ring phase, each replayed at least once
 
 
+@pytest.mark.parametrize("check", ["nnc_frmc", "rme"])
+def test_pipelined_stream_set_equals_plain(check):
+    """Pipelined time steps (every stream's lag-2/3 motion path on a side
+    stream beside the previous step's FSR; rfsr_reconstruct_batch_part)
+    against the plain batched recursion: identical outputs at every step.
+    Four streams of different sizes, nine steps, no synchronisation between
+    steps (each step's outputs are cloned on the main stream)."""
+    R = need_gpu()
+    sizes = [(64, 64), (48, 80), (32, 96), (128, 160)]
+    T = 9
+    me, fsr = R.MEParams(search=6, check=check), R.FSRParams(iters=40)
+    data = []
+    for i, (H, W) in enumerate(sizes):
+        rng = np.random.default_rng(500 + i)
+        frames, _ = synth.video_translate_edges(T, H, W, rng, max_step=2, n_edges=2)
+        masks = synth.mask_sequence("dynamic" if i % 2 else "fixed", T, H, W, rng)
+        data.append(([dev(x) for x in synth.measured(frames, masks)], [dev(x) for x in masks]))
+    torch.cuda.synchronize()
+    res = []
+    for pipelined in (False, True):
+        ss = R.StreamSet(sizes, me, fsr, graphs=False, pipelined=pipelined)
+        outs = []
+        for t in range(T):
+            got = ss.step([d[0][t] for d in data], [d[1][t] for d in data])
+            outs.append([(o.clone(), u.clone()) for o, u in got])
+        torch.cuda.synchronize()
+        res.append([[(host(o), host(u)) for o, u in step] for step in outs])
+    for t in range(T):
+        for s in range(len(sizes)):
+            assert np.array_equal(res[0][t][s][0], res[1][t][s][0]), (t, s)
+            assert np.array_equal(res[0][t][s][1], res[1][t][s][1]), (t, s)
+
+
 def test_graph_replays_equal_eager():
     R = need_gpu()
     me, fsr = R.MEParams(search=6, check="nnc_frmc"), R.FSRParams(iters=30)
