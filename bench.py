@@ -340,7 +340,9 @@ def main(argv=None):
                    "pipelined": not a.no_pipeline},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
                        "p50_steady": round(percentile(lat_steady, 50), 3) if lat_steady else None,
-                       "p99_steady": round(percentile(lat_steady, 99), 3) if lat_steady else None},
+                       "p99_steady": round(percentile(lat_steady, 99), 3) if lat_steady else None,
+                       "definition": "completion of frame t after the completion of frame t-1 (its lag-1 "
+                                     "reference); steady: frames with three references"},
         "stage_ms_mean": {"me_and_check": round(float(np.mean(me_ms)), 4),
                           "projection": round(float(np.mean(proj_ms)), 4),
                           "fsr": round(float(np.mean(fsr_ms)), 4),
