@@ -234,10 +234,11 @@ rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, 
  * the rest of the frame.  With first < nref it requires a preceding
  * rfsr_frame_motion(..., first, ...) with the same arguments and workspace,
  * ordered before this call by the caller (same stream, or an event); with
- * first == nref it is rfsr_reconstruct_frame.  The two calls use separate
- * 1 KB job-table slots of the workspace (rfsr_workspace_bytes covers both),
- * so the second may be enqueued while the first is still running; the
- * workspace must not be used by another frame until the second completes.
+ * first == nref it is rfsr_reconstruct_frame.  Its stage events cover its
+ * own work ([1]: after the ME and checks of references 0..first-1).  The two
+ * calls write their job tables to separate 1 KB slots of the workspace
+ * (rfsr_workspace_bytes covers both); the workspace must not be used by
+ * another frame until the second call's work has completed.
  * Errors: as rfsr_reconstruct_frame; RFSR_EINVAL for first outside 0..nref. */
 rfsr_status rfsr_frame_motion(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,
                               const uint8_t* const* ref_recon,
