@@ -2,8 +2,9 @@
 finish: the CPU-sized 128x128 recursion (fixed mask, R = 8, RME and RMC
 each), end to end against the oracle, and the 1920x1080 recursive frame in
 the configuration bench.py times (dynamic mask, R = 9, NNC -> FRMC, K = 100,
-three references that are the GPU's own reconstructions), on sampled pixels
-and blocks the oracle recomputes one by one from the same inputs."""
+three references that are the GPU's own reconstructions, consecutive frames
+pipelined), on sampled pixels and blocks the oracle recomputes one by one
+from the same inputs."""
 import numpy as np
 import pytest
 import torch
@@ -53,7 +54,7 @@ def test_1080p_recursive_frame_sampled():
     frames, masks = synth.workload_c2(n=4, h=H, w=W)
     meas = synth.measured(frames, masks)
     me_g, fsr_g = R.MEParams(search=9, check="nnc_frmc"), R.FSRParams(iters=100)
-    seq = R.Sequence(H, W, me_g, fsr_g)
+    seq = R.Sequence(H, W, me_g, fsr_g, pipelined=True)   # as bench.py runs it
     for t in range(3):
         seq.push(dev(meas[t]), dev(masks[t]))
     refs = [(host(r[0]).copy(), meas[2 - k], masks[2 - k]) for k, r in enumerate(reversed(seq.ring[-3:]))]
