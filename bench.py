@@ -83,7 +83,7 @@ def traffic_from_profile(kernel_src: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(frames, masks, me_o, fsr_o, crop=128):
+def cpu_baseline(frames, masks, me_o, fsr_o, crop=176):
     """The oracle (float64 FSR, integer ME) on a bounded sample: frame 3 of the
     workload (three references), a crop x crop window at the frame centre."""
     import numpy as np
