@@ -26,7 +26,7 @@ from .me import (template_offsets, cost_at, reverse_cost_at, n_map, forward_me,
 from .checks import (frmc_offsets, rmc_offsets, reverse_me, rme_accept, rmc_accept, rmc_accept_at,
                      median3x3, nnc_accept, motion_check, CHECKS)
 from .projection import project
-from .fsr import (rho_table, fsr_spatial, fsr_spectral, gather_supports, fsr_frame,
+from .fsr import (rho_table, prior_table, fsr_spatial, fsr_spectral, gather_supports, fsr_frame,
                   fsr_frame_concealed, fsr_pairs_spatial, fsr_pairs_spectral, fsr_pairs_blocks_out)
 from .frame import (MEParams, FSRParams, reconstruct_frame, reconstruct_sequence,
                     quantize, psnr)
@@ -36,7 +36,7 @@ __all__ = [
     "template_offsets", "cost_at", "reverse_cost_at", "n_map", "forward_me",
     "forward_me_at", "frmc_offsets", "rmc_offsets", "reverse_me", "rme_accept",
     "rmc_accept", "rmc_accept_at", "median3x3", "nnc_accept", "motion_check", "CHECKS", "project",
-    "rho_table", "fsr_spatial", "fsr_spectral", "gather_supports", "fsr_frame", "fsr_frame_concealed",
+    "rho_table", "prior_table", "fsr_spatial", "fsr_spectral", "gather_supports", "fsr_frame", "fsr_frame_concealed",
     "fsr_pairs_spatial", "fsr_pairs_spectral", "fsr_pairs_blocks_out",
     "MEParams", "FSRParams", "reconstruct_frame", "reconstruct_sequence",
     "quantize", "psnr", "gaussian_window", "ssim", "ssim_map", "ssim_bruteforce",

@@ -37,6 +37,8 @@ class FSRParams:
     proj_weight: float = 1.0
     overwrite: str = "dfsr"
     concealed_weight: float = 0.0     # delta; > 0: blocks in raster order (fsr_frame_concealed)
+    prior_sigma: float = 0.0          # frequency-weighting prior (0: off), fsr.prior_table
+    stop_ratio: float = 0.0           # residual-energy early stop (0: off)
 
 
 def quantize(out):
@@ -69,11 +71,14 @@ def reconstruct_frame(cur, cur_mask, refs, me: MEParams, fsr: FSRParams, track_g
     fields = motion_fields(cur, cur_mask, refs, me)
     values, cls = project(cur, cur_mask, fields)
     if fsr.concealed_weight > 0:
+        if fsr.prior_sigma > 0 or fsr.stop_ratio > 0:
+            raise ValueError("the prior and the early stop are not combined with concealed weighting")
         out, gaps = fsr_frame_concealed(values, cls, fsr.concealed_weight, fsr.block, fsr.support,
                                         fsr.rho, fsr.gamma, fsr.iters, fsr.proj_weight, fsr.overwrite)
     else:
         out, gaps = fsr_frame(values, cls, fsr.block, fsr.support, fsr.rho, fsr.gamma,
-                              fsr.iters, fsr.proj_weight, fsr.overwrite, track_gaps)
+                              fsr.iters, fsr.proj_weight, fsr.overwrite, track_gaps,
+                              prior_sigma=fsr.prior_sigma, stop_ratio=fsr.stop_ratio)
     return dict(out=out, out_u8=quantize(out), values=values, cls=cls, fields=fields,
                 gaps=gaps)
 

@@ -26,7 +26,17 @@ type) FSR of the literature the paper cites; the readings used here:
   * Model g = sum_k c_k phi_k; the block output is Re g on the block pixels.
   * Overwrite: D-FSR writes the measured values over the model, R-FSR the
     measured and the projected values (Sec. 3.2).
-  * No frequency-weighting prior, no early stop; W0 = 0 gives g = 0.
+  * W0 = 0 gives g = 0.
+  * Options of the FSR literature that the paper's configuration does not
+    use (both off by default):
+      - frequency-weighting prior: the pick maximises prior_k |R_k|^2 with
+        prior_k = sigma ** |k|, |k| the Euclidean distance of
+        (min(k1, M-k1), min(k2, M-k2)) from DC (0 < sigma <= 1), favouring
+        low frequencies; the update dlt is unchanged;
+      - residual-energy early stop: a block stops before iteration i >= 1
+        once its pick's criterion value (prior_b |R_b|^2, or |R_b|^2) is
+        below stop_ratio times that of iteration 0; a stopped block picks
+        -1 and changes nothing.
 
 Two forms are given: `fsr_spatial` recomputes the weighted residual DFT from
 the spatial residual every iteration (the plain form), `fsr_spectral`
@@ -46,6 +56,15 @@ def rho_table(rho: float, M: int = 32) -> np.ndarray:
     return rho ** d
 
 
+def prior_table(sigma: float, M: int = 32) -> np.ndarray:
+    """(M, M) frequency-weighting prior sigma ** |k| (all ones for sigma = 0,
+    the option switched off)."""
+    if sigma == 0:
+        return np.ones((M, M))
+    f = np.minimum(np.arange(M), M - np.arange(M)).astype(np.float64)
+    return sigma ** np.sqrt(f[:, None] ** 2 + f[None, :] ** 2)
+
+
 def _basis(b1, b2, M):
     """phi_b[m,n] = exp(2 pi i b1 m / M) * exp(2 pi i b2 n / M)."""
     m = np.arange(M, dtype=np.float64)
@@ -54,14 +73,18 @@ def _basis(b1, b2, M):
     return e1[:, :, None] * e2[:, None, :]
 
 
-def fsr_spatial(s, w, gamma, K, track_gaps=False):
+def fsr_spatial(s, w, gamma, K, track_gaps=False, stop_ratio=0.0, prior=None):
     """Greedy FSR on a batch of supports (independent blocks).
 
     s: (nb, M, M) real or complex samples (0 where unknown), w: (nb, M, M)
     real weights.  Returns (c (nb,M,M) complex coefficients,
-    picks (nb,K) flat bin indices, gaps (nb,) or None, (energies, chosen)):
-    energies[i] = sum w |r|^2 after iteration i, chosen[i] = |R_b|^2 of the
-    bin chosen at iteration i.
+    picks (nb,K) flat bin indices (-1 after an early stop), gaps (nb,) or
+    None, (energies, chosen)): energies[i] = sum w |r|^2 after iteration i,
+    chosen[i] = the criterion value (|R_b|^2, times prior_b with a prior) of
+    the bin chosen at iteration i (0 once stopped).
+
+    prior: optional (M, M) frequency weights (`prior_table`); stop_ratio > 0:
+    residual-energy early stop (module docstring).
 
     With track_gaps, gaps[b] is the minimum over iterations of
     (E_best - E_next) / E_best, where E_next excludes the chosen bin and,
@@ -80,16 +103,32 @@ def fsr_spatial(s, w, gamma, K, track_gaps=False):
     picks = np.zeros((nb, K), np.int64)
     gaps = np.full(nb, np.inf) if track_gaps else None
     herm = np.full(nb, bool(np.isrealobj(s) or not np.any(np.imag(s))))
+    pw = None if prior is None else np.asarray(prior, np.float64).reshape(M * M)
     energies = []      # weighted residual energy sum w|r|^2 after each iteration
-    chosen = []        # |R_b|^2 of the chosen bin at each iteration
+    chosen = []        # criterion value of the chosen bin at each iteration
+    active = np.ones(nb, bool)
+    E0 = None
     for it in range(K):
         Rs = np.fft.fft2(w * r).reshape(nb, M * M)
         E = Rs.real ** 2 + Rs.imag ** 2
+        if pw is not None:
+            E = E * pw[None]
         b = E.argmax(axis=1)
-        picks[:, it] = b
         Rb = Rs[idx, b]
-        chosen.append(E[idx, b])
-        dlt = np.where(safe, gamma * Rb / np.where(safe, W0, 1.0), 0.0)
+        if stop_ratio > 0:
+            Eb = E[idx, b]
+            if it == 0:
+                E0 = Eb.copy()
+            else:
+                thr = stop_ratio * E0
+                if track_gaps:   # a decision within rounding of the threshold is a near tie too
+                    with np.errstate(divide="ignore", invalid="ignore"):
+                        tg = np.where(active & (Eb > 0), np.abs(Eb - thr) / Eb, np.inf)
+                    gaps = np.minimum(gaps, tg)
+                active &= Eb >= thr
+        picks[:, it] = np.where(active, b, -1)
+        chosen.append(np.where(active, E[idx, b], 0.0))
+        dlt = np.where(safe & active, gamma * Rb / np.where(safe, W0, 1.0), 0.0)
         c[idx, b] += dlt
         b1, b2 = b // M, b % M
         r -= dlt[:, None, None] * _basis(b1, b2, M)
@@ -102,14 +141,14 @@ def fsr_spatial(s, w, gamma, K, track_gaps=False):
             Es[idx[hp], partner[hp]] = -np.inf
             E2 = Es.max(axis=1)
             with np.errstate(divide="ignore", invalid="ignore"):
-                g = np.where(E1 > 0, (E1 - E2) / E1, np.inf)
+                g = np.where(active & (E1 > 0), (E1 - E2) / E1, np.inf)
             gaps = np.minimum(gaps, g)
             herm &= partner == b
         energies.append((w * np.abs(r) ** 2).sum(axis=(1, 2)))
     return c.reshape(nb, M, M), picks, gaps, (energies, chosen)
 
 
-def fsr_spectral(s, w, gamma, K):
+def fsr_spectral(s, w, gamma, K, stop_ratio=0.0, prior=None):
     """Same loop with an in-place residual-spectrum update
     R_k <- R_k - dlt * W_{(k-b) mod M}.  Returns (c, picks)."""
     s = np.asarray(s)
@@ -123,12 +162,22 @@ def fsr_spectral(s, w, gamma, K):
     c = np.zeros((nb, M * M), np.complex128)
     picks = np.zeros((nb, K), np.int64)
     m = np.arange(M)
+    pw = None if prior is None else np.asarray(prior, np.float64).reshape(M * M)
+    active = np.ones(nb, bool)
+    E0 = None
     for it in range(K):
         Rf = R.reshape(nb, M * M)
         E = Rf.real ** 2 + Rf.imag ** 2
+        if pw is not None:
+            E = E * pw[None]
         b = E.argmax(axis=1)
-        picks[:, it] = b
-        dlt = np.where(safe, gamma * Rf[idx, b] / np.where(safe, W0, 1.0), 0.0)
+        if stop_ratio > 0:
+            if it == 0:
+                E0 = E[idx, b].copy()
+            else:
+                active &= E[idx, b] >= stop_ratio * E0
+        picks[:, it] = np.where(active, b, -1)
+        dlt = np.where(safe & active, gamma * Rf[idx, b] / np.where(safe, W0, 1.0), 0.0)
         c[idx, b] += dlt
         b1, b2 = b // M, b % M
         i1 = (m[None, :] - b1[:, None]) % M
@@ -281,15 +330,18 @@ def gather_supports(values, cls, blocks, B=4, M=32, proj_weight=1.0):
 
 
 def fsr_blocks_out(values, cls, blocks, B=4, M=32, rho=0.7, gamma=0.5, K=100,
-                   proj_weight=1.0, overwrite="dfsr", track_gaps=True, chunk=2048):
+                   proj_weight=1.0, overwrite="dfsr", track_gaps=True, chunk=2048,
+                   prior_sigma=0.0, stop_ratio=0.0):
     """FSR of the listed blocks.  Returns (out (nb,B,B) float64, gaps (nb,))."""
     blocks = np.asarray(blocks, np.int64).reshape(-1, 2)
     tab = rho_table(rho, M)
+    prior = prior_table(prior_sigma, M) if prior_sigma > 0 else None
     outs, gaps = [], []
     for i in range(0, blocks.shape[0], chunk):
         blk = blocks[i:i + chunk]
         s, a = gather_supports(values, cls, blk, B, M, proj_weight)
-        c, _, g, _ = fsr_spatial(s, a * tab[None], gamma, K, track_gaps=track_gaps)
+        c, _, g, _ = fsr_spatial(s, a * tab[None], gamma, K, track_gaps=track_gaps, stop_ratio=stop_ratio,
+                                 prior=prior)
         out = synthesize(c, B)
         # overwrite with measured (D-FSR) or measured + projected (R-FSR) values
         for j, (bi, bj) in enumerate(blk):
@@ -361,11 +413,11 @@ def all_blocks(H, W, B=4):
 
 
 def fsr_frame(values, cls, B=4, M=32, rho=0.7, gamma=0.5, K=100, proj_weight=1.0,
-              overwrite="dfsr", track_gaps=True):
+              overwrite="dfsr", track_gaps=True, prior_sigma=0.0, stop_ratio=0.0):
     """FSR of a whole frame.  Returns (out (H,W) float64, gaps (H/B, W/B))."""
     H, W = values.shape
     blocks = all_blocks(H, W, B)
     out_b, gaps = fsr_blocks_out(values, cls, blocks, B, M, rho, gamma, K, proj_weight,
-                                 overwrite, track_gaps)
+                                 overwrite, track_gaps, prior_sigma=prior_sigma, stop_ratio=stop_ratio)
     out = out_b.reshape(H // B, W // B, B, B).transpose(0, 2, 1, 3).reshape(H, W)
     return out, gaps.reshape(H // B, W // B)

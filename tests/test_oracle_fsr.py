@@ -279,3 +279,127 @@ def test_pairs_spatial_and_spectral_forms_agree():
     assert np.allclose(ca, cb, atol=1e-8 * np.abs(ca).max())
     model = np.fft.ifft2(ca, axes=(1, 2))
     assert np.abs(model.imag).max() < 1e-9 * np.abs(model.real).max()
+
+
+# ------------------------------------------------------------- early stop --
+def test_early_stop_zero_ratio_is_plain_loop():
+    rng = np.random.default_rng(8)
+    s = rng.normal(100, 30, (5, 32, 32))
+    w = (rng.random((5, 32, 32)) < 0.3) * O.rho_table(0.7)[None]
+    a = O.fsr_spatial(s, w, 0.5, 40)
+    b = O.fsr_spatial(s, w, 0.5, 40, stop_ratio=0.0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_early_stop_single_basis_iteration_count():
+    """Uniform weights, one complex basis function: the chosen energy after i
+    iterations is (1-gamma)^(2i) E0, so with ratio r the loop stops before
+    the first i with (1-gamma)^(2i) < r."""
+    M, g = 32, 0.5
+    m = np.arange(M)
+    s = 50 * np.exp(2j * np.pi * (3 * m[:, None] + 5 * m[None, :]) / M)[None]
+    for r, n in ((0.5, 1), (0.2, 2), (0.01, 4), (1e-4, 7)):
+        c, picks, _, _ = O.fsr_spatial(s, np.ones((1, M, M)), g, 20, stop_ratio=r)
+        done = int((picks[0] >= 0).sum())
+        assert done == n, (r, done)
+        assert (picks[0, done:] == -1).all()
+        assert np.isclose(np.abs(c[0, 3, 5]), 50 * (1 - (1 - g) ** n))
+
+
+def test_early_stop_prefix_of_full_loop():
+    rng = np.random.default_rng(9)
+    s = rng.normal(100, 30, (6, 32, 32))
+    w = (rng.random((6, 32, 32)) < 0.3) * O.rho_table(0.7)[None]
+    full = O.fsr_spatial(s, w, 0.5, 60)[1]
+    stop = O.fsr_spatial(s, w, 0.5, 60, stop_ratio=1e-3)[1]
+    for i in range(6):
+        n = int((stop[i] >= 0).sum())
+        assert 1 <= n <= 60
+        assert np.array_equal(stop[i, :n], full[i, :n])
+
+
+# ------------------------------------------------- frequency-weighting prior --
+def test_prior_table_closed_form():
+    s = 0.8
+    T = O.prior_table(s, 32)
+    assert T[0, 0] == 1.0 and np.isclose(T[0, 1], s) and np.isclose(T[1, 1], s ** np.sqrt(2))
+    assert np.isclose(T[16, 16], s ** np.sqrt(512)) and np.isclose(T[31, 30], s ** np.sqrt(5))
+    k = np.arange(32)
+    assert np.array_equal(T, T[(-k) % 32][:, (-k) % 32])      # even: conjugate bins weigh the same
+    assert (O.prior_table(0.0, 32) == 1).all()
+
+
+def test_prior_off_is_plain_loop():
+    rng = np.random.default_rng(11)
+    s = rng.normal(100, 30, (4, 32, 32))
+    w = (rng.random((4, 32, 32)) < 0.3) * O.rho_table(0.7)[None]
+    a = O.fsr_spatial(s, w, 0.5, 30)
+    b = O.fsr_spatial(s, w, 0.5, 30, prior=O.prior_table(0.0, 32))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def _brute_prior_loop(s, w, prior, gamma, K):
+    """Direct loops on one small support: residual DFT as explicit sums, the
+    pick maximising prior * |R|^2 (first in row-major order), the usual
+    update.  Returns the picks and the coefficients."""
+    M = w.shape[0]
+    r = s.astype(complex).copy()
+    W0 = w.sum()
+    c = np.zeros((M, M), complex)
+    picks = []
+    for _ in range(K):
+        best, bk = -1.0, None
+        for k1 in range(M):
+            for k2 in range(M):
+                R = 0j
+                for m in range(M):
+                    for n in range(M):
+                        R += w[m, n] * r[m, n] * np.exp(-2j * np.pi * (k1 * m + k2 * n) / M)
+                crit = prior[k1, k2] * abs(R) ** 2
+                if crit > best:
+                    best, bk, Rb = crit, (k1, k2), R
+        d = gamma * Rb / W0
+        c[bk] += d
+        picks.append(bk[0] * M + bk[1])
+        m = np.arange(M)
+        r -= d * np.exp(2j * np.pi * (bk[0] * m[:, None] + bk[1] * m[None, :]) / M)
+    return np.array(picks), c
+
+
+def test_prior_against_brute_force_loops():
+    rng = np.random.default_rng(12)
+    M = 8
+    s = rng.normal(0, 1, (M, M)) + 1j * rng.normal(0, 1, (M, M))
+    w = rng.random((M, M)) * (rng.random((M, M)) < 0.6)
+    prior = O.prior_table(0.7, M)
+    picks, c = _brute_prior_loop(s, w, prior, 0.5, 5)
+    co, po, _, _ = O.fsr_spatial(s[None], w[None], 0.5, 5, prior=prior)
+    assert np.array_equal(po[0], picks)
+    assert np.allclose(co[0], c, atol=1e-12 * np.abs(c).max())
+    # the prior changes the picks here (without it the loop differs)
+    assert not np.array_equal(O.fsr_spatial(s[None], w[None], 0.5, 5)[1][0], picks)
+
+
+def test_prior_prefers_the_lower_frequency():
+    """Two real cosines, the higher one with 1.1x the amplitude: the plain
+    loop picks the higher first (energy ratio 1.21), the prior with sigma 0.9
+    the lower (0.9 vs 1.21 * 0.9^5)."""
+    M = 32
+    m = np.arange(M)
+    s = (np.cos(2 * np.pi * 1 * m / M)[None, :] + 1.1 * np.cos(2 * np.pi * 5 * m / M)[None, :]) * np.ones((M, 1))
+    w = np.ones((1, M, M))
+    first_plain = O.fsr_spatial(s[None], w, 0.5, 1)[1][0, 0] % M
+    first_prior = O.fsr_spatial(s[None], w, 0.5, 1, prior=O.prior_table(0.9, M))[1][0, 0] % M
+    assert first_plain in (5, M - 5) and first_prior in (1, M - 1)
+
+
+def test_prior_and_stop_spatial_and_spectral_forms_agree():
+    # complex samples: no conjugate-partner ties, so both forms pick the same bins
+    rng = np.random.default_rng(13)
+    s = rng.normal(100, 30, (5, 32, 32)) + 1j * rng.normal(0, 30, (5, 32, 32))
+    w = (rng.random((5, 32, 32)) < 0.3) * O.rho_table(0.7)[None]
+    prior = O.prior_table(0.85, 32)
+    ca, pa, _, _ = O.fsr_spatial(s, w, 0.5, 40, prior=prior, stop_ratio=1e-3)
+    cb, pb = O.fsr_spectral(s, w, 0.5, 40, prior=prior, stop_ratio=1e-3)
+    assert np.array_equal(pa, pb)
+    assert np.allclose(ca, cb, atol=1e-9 * np.abs(ca).max())
