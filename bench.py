@@ -127,7 +127,8 @@ def run_multistream(a, dev):
     meas = [[torch.from_numpy(synth.measured(f[t], m[t])).to(dev) for t in range(T)] for f, m in data]
     masks = [[torch.from_numpy(m[t]).to(dev) for t in range(T)] for _, m in data]
     me = R.MEParams(search=a.search, check=a.check)
-    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs, concealed_weight=a.concealed)
+    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs, concealed_weight=a.concealed,
+                      prior_sigma=a.prior, stop_ratio=a.stop)
     px_step = sum(h * w for h, w in sizes)
 
     pipelined = not a.no_pipeline
@@ -208,6 +209,10 @@ def main(argv=None):
     ap.add_argument("--search", type=int, default=9)
     ap.add_argument("--check", default="nnc_frmc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prior", type=float, default=0.0,
+                    help="FSR frequency-weighting prior sigma (0: off; an FSR-literature option)")
+    ap.add_argument("--stop", type=float, default=0.0,
+                    help="FSR residual-energy early-stop ratio (0: off; an FSR-literature option)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="no overlap of consecutive frames / time steps (each frame's motion path after the "
                          "previous frame)")
@@ -256,7 +261,8 @@ def main(argv=None):
     outs = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(F)]
     outs_u8 = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(F)]
     me = R.MEParams(search=a.search, check=a.check)
-    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs, concealed_weight=a.concealed)
+    fsr = R.FSRParams(iters=a.iters, precision=a.precision, pairs=a.pairs, concealed_weight=a.concealed,
+                      prior_sigma=a.prior, stop_ratio=a.stop)
     stream = torch.cuda.current_stream()
     seq = R.Sequence(H, W, me, fsr, device=dev, pipelined=not a.no_pipeline)
     torch.cuda.synchronize()   # inputs resident before any frame is enqueued
@@ -309,6 +315,10 @@ def main(argv=None):
                 "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4), "traffic": traffic,
                 "flops_per_launch": flops, "avg_launch_ms": round(fsr_avg_s * 1e3, 4)}
+    if a.stop:
+        roofline["note"] = "flops counted for K iterations per block; the early stop runs fewer"
+    if a.prior:
+        roofline["note_prior"] = "the prior adds one multiply per bin and iteration, not counted"
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -335,7 +345,9 @@ def main(argv=None):
                                f"4x4 blocks, 32x32 support, rho=0.7, gamma=0.5, K={a.iters}, 3 references"
                                + ("" if a.precision == "fp64" else f", block DFT {a.precision}")
                                + (", conjugate-pair FSR" if a.pairs else "")
-                               + (f", concealed weighting {a.concealed}" if a.concealed else ""),
+                               + (f", concealed weighting {a.concealed}" if a.concealed else "")
+                               + (f", frequency prior sigma {a.prior}" if a.prior else "")
+                               + (f", early stop ratio {a.stop}" if a.stop else ""),
                    "frames": F, "height": H, "width": W, "parallelism": "single GPU",
                    "pipelined": not a.no_pipeline},
         "latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),

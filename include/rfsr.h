@@ -103,6 +103,8 @@ typedef struct {
     int32_t precision;   /* rfsr_precision of the block DFT (0 = float64)     */
     int32_t pairs;       /* 0: complex single bins; 1: conjugate pairs        */
     double concealed_weight; /* delta, 0 <= delta <= 1 (0 = independent blocks) */
+    double prior_sigma;  /* frequency-weighting prior, 0 (off) or 0 < sigma <= 1 */
+    double stop_ratio;   /* residual-energy early stop, 0 (off) or 0 < ratio < 1 */
 } rfsr_fsr_params;
 
 /* Basis selection.  pairs = 0 (default): every iteration adds one complex
@@ -123,7 +125,20 @@ typedef struct {
  * step never share a support), i.e. 5 (H/4 - 1) + W/4 dependent launches per
  * frame.  rfsr_reconstruct_batch runs the steps of all its frames together
  * (one launch per step holding every frame's blocks of that step), so many
- * streams fill the GPU that one frame's wavefront leaves idle. */
+ * streams fill the GPU that one frame's wavefront leaves idle.
+ *
+ * Two options of the FSR literature that the paper's configuration does not
+ * use (both 0 = off by default; float64 FFT, complex single bins and
+ * independent blocks only, else RFSR_EUNSUPPORTED):
+ *   prior_sigma: the pick maximises prior_k |R_k|^2 with prior_k =
+ *     sigma^|k|, |k| the Euclidean distance of (min(k1, 32-k1),
+ *     min(k2, 32-k2)) from DC, so low frequencies are favoured; the update
+ *     is unchanged.
+ *   stop_ratio: a block stops before iteration i >= 1 once its pick's
+ *     criterion value (prior_b |R_b|^2, or |R_b|^2) falls below stop_ratio
+ *     times that of its first iteration.
+ * They run in a kernel of their own, so the default loop carries no test
+ * for them. */
 
 /* Arithmetic of the block DFT that starts FSR (R = DFT(w s), W = DFT(w));
  * the iterations are float64 in every case.

@@ -37,7 +37,8 @@ class _FSRParams(ctypes.Structure):
                 ("iters", ctypes.c_int32), ("overwrite", ctypes.c_int32),
                 ("rho", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("proj_weight", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("pairs", ctypes.c_int32), ("concealed_weight", ctypes.c_double)]
+                ("pairs", ctypes.c_int32), ("concealed_weight", ctypes.c_double),
+                ("prior_sigma", ctypes.c_double), ("stop_ratio", ctypes.c_double)]
 
 
 @dataclass
@@ -65,11 +66,13 @@ class FSRParams:
     precision: str = "fp64"     # block DFT: "fp64", "bf16x3" or "fp16x3" (matrix cores)
     concealed_weight: float = 0.0   # delta > 0: raster-order blocks (wavefront), single frames only
     pairs: bool = False             # real-valued FSR: conjugate pairs per iteration
+    prior_sigma: float = 0.0        # frequency-weighting prior (0: off)
+    stop_ratio: float = 0.0         # residual-energy early stop (0: off)
 
     def c(self) -> _FSRParams:
         return _FSRParams(self.block, self.support, self.iters, OVERWRITE[self.overwrite],
                           self.rho, self.gamma, self.proj_weight, PRECISION[self.precision],
-                          int(self.pairs), self.concealed_weight)
+                          int(self.pairs), self.concealed_weight, self.prior_sigma, self.stop_ratio)
 
 
 class FrameDesc(ctypes.Structure):

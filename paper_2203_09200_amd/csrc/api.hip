@@ -14,7 +14,7 @@ using namespace rfsr;
 
 namespace {
 
-constexpr int32_t kVersion = 10500;   // 1.5.0
+constexpr int32_t kVersion = 10600;   // 1.6.0
 constexpr int kMaxBatch = 4096;
 
 rfsr_status from_hip(hipError_t e) { return e == hipSuccess ? RFSR_OK : RFSR_EDEVICE; }
@@ -47,7 +47,12 @@ rfsr_status check_fsr(const rfsr_fsr_params* p) {
     if (p->precision < RFSR_PREC_FP64 || p->precision > RFSR_PREC_FP16X3) return RFSR_EINVAL;
     if (!(p->concealed_weight >= 0.0 && p->concealed_weight <= 1.0)) return RFSR_EINVAL;
     if (p->pairs != 0 && p->pairs != 1) return RFSR_EINVAL;
+    if (!(p->prior_sigma >= 0.0 && p->prior_sigma <= 1.0)) return RFSR_EINVAL;
+    if (!(p->stop_ratio >= 0.0 && p->stop_ratio < 1.0)) return RFSR_EINVAL;
     if (p->pairs && p->concealed_weight > 0.0) return RFSR_EUNSUPPORTED;
+    if ((p->prior_sigma > 0.0 || p->stop_ratio > 0.0) &&
+        (p->pairs || p->concealed_weight > 0.0 || p->precision != RFSR_PREC_FP64))
+        return RFSR_EUNSUPPORTED;
     if (p->block != kBlock || p->support != kSupport) return RFSR_EUNSUPPORTED;
     return RFSR_OK;
 }
@@ -395,7 +400,7 @@ hipError_t run_batch(const rfsr_frame_desc* frames, int n, const rfsr_me_params&
                            reinterpret_cast<uint32_t*>(const_cast<uint8_t*>(img)));
         e = hipGetLastError();
     }
-    if (e == hipSuccess && part.finish()) e = launch_fsr_tables(tab, fsr->rho, s);
+    if (e == hipSuccess && part.finish()) e = launch_fsr_tables(tab, fsr->rho, fsr->prior_sigma, s);
     if (e == hipSuccess && !p.refs.empty()) {
         e = launch_windows(jf, p.win, s);
         if (e == hipSuccess) e = launch_motion(jr, p.tiles, p.px_refs, p.frmc, me, nullptr, s);
@@ -527,7 +532,7 @@ rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32
     fj.vpitch = pitch;
     fj.H = H;
     fj.W = W;
-    hipError_t e = launch_fsr_tables(tab, fsr->rho, s);
+    hipError_t e = launch_fsr_tables(tab, fsr->rho, fsr->prior_sigma, s);
     if (e == hipSuccess) e = launch_fsr(single(fj), (H / kBlock) * (W / kBlock), *fsr, tab, s);
     return from_hip(e);
 }

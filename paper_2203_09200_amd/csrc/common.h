@@ -80,8 +80,9 @@ __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_
 
 // Tables used by the FSR kernel (written by fsr_tables_kernel).
 struct FsrTables {
-    double rho[kSupport * kSupport];  // rho ** distance to the support centre
-    double tw[2 * kSupport];          // exp(-2 pi i t / 32), t = 0..31, (re, im)
+    double rho[kSupport * kSupport];    // rho ** distance to the support centre
+    double tw[2 * kSupport];            // exp(-2 pi i t / 32), t = 0..31, (re, im)
+    double prior[kSupport * kSupport];  // frequency-weighting prior sigma ** |k| (1 when off)
 };
 
 // ------------------------------------------------------------------- jobs --
@@ -209,7 +210,7 @@ __host__ __device__ inline int frmc_groups(int H, int W) { return (H * W + kFrmc
 
 // --------------------------------------------------------------- launches --
 // Each returns hipSuccess or the launch error.
-hipError_t launch_fsr_tables(FsrTables* t, double rho, hipStream_t s);
+hipError_t launch_fsr_tables(FsrTables* t, double rho, double prior_sigma, hipStream_t s);
 // FSR over all `total_blocks` blocks of the frames in `js`.  With a
 // concealed weighting and a job table, `host_frames` is the host copy of the
 // table (frame sizes for the wavefront grid).

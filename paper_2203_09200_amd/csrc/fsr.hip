@@ -169,13 +169,13 @@ __device__ __forceinline__ double wave_allmax_f64(double v) {
 // reductions, one per step, and four readlanes); only when several lanes
 // share the maximal high word (the first iterations, while the spectrum is
 // Hermitian, and near ties) are their low words reduced as well.  Returns the
-// low word of the maximum (its 5 low bits carry the row code) and, in
-// `owner`, the first lane holding it: the lanes holding one packed value all
-// own the same row, so the first is the smallest column.
-__device__ __forceinline__ uint32_t wave_argmax_packed(double v, int& owner) {
+// low word of the maximum (its 5 low bits carry the row code), in `mh` its
+// high word and in `owner` the first lane holding it: the lanes holding one
+// packed value all own the same row, so the first is the smallest column.
+__device__ __forceinline__ uint32_t wave_argmax_packed(double v, int& owner, uint32_t& mh) {
     const uint32_t hi = (uint32_t)__double2hiint(v);
     const uint32_t lo = (uint32_t)__double2loint(v);
-    const uint32_t mh = wave_max_u32(hi);
+    mh = wave_max_u32(hi);
     unsigned long long cand = __ballot(hi == mh);
     if (__popcll(cand) == 1) {
         owner = (int)__builtin_ctzll(cand);
@@ -355,11 +355,15 @@ __device__ __forceinline__ void dft_mfma(const double (&xs)[16], const double (&
 
 }  // namespace
 
-__global__ void fsr_tables_kernel(FsrTables* t, double rho) {
+__global__ void fsr_tables_kernel(FsrTables* t, double rho, double sigma) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kSupport * kSupport) {
         const double dm = (i >> 5) - 15.5, dn = (i & 31) - 15.5;
         t->rho[i] = pow(rho, sqrt(dm * dm + dn * dn));
+        // frequency distance of bin (k1, k2) from DC, both signs of k
+        const int k1 = i >> 5, k2 = i & 31;
+        const double f1 = min(k1, kSupport - k1), f2 = min(k2, kSupport - k2);
+        t->prior[i] = sigma > 0.0 ? pow(sigma, sqrt(f1 * f1 + f2 * f2)) : 1.0;
     }
     if (i < kSupport) {
         double s, c;
@@ -386,10 +390,16 @@ __global__ void fsr_tables_kernel(FsrTables* t, double rho) {
 // The loop keeps only registers j = 0..8 of the layout (rows 0..8 and
 // 16..24, which contain every row 0..16 or its conjugate), updates
 // R_k -= dlt W(k - b) + conj(dlt) W(k + b) and halves dlt when b = -b.
-template <int PREC, bool CONC, bool PAIRS>
+//
+// OPT (float64 FFT, independent blocks, complex bins only): bit 0 weighs the
+// pick's energies with the frequency prior of `tab`, bit 1 stops a block once
+// its pick's (weighted) energy falls below stop_ratio times its first.
+template <int PREC, bool CONC, bool PAIRS, int OPT = 0>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void fsr_block_kernel(
     Jobs<FrameJob> js, int total, const FsrTables* __restrict__ tab, int K, double gamma,
-    double projw, int overwrite, double delta, int step, int bi0) {
+    double projw, int overwrite, double delta, int step, int bi0, double stop_ratio) {
+    static_assert(OPT == 0 || (PREC == RFSR_PREC_FP64 && !CONC && !PAIRS), "options: plain loop only");
+    constexpr bool PRIOR = (OPT & 1) != 0, STOP = (OPT & 2) != 0;
     // W table (32 x 32 complex double); the transpose planes reuse it.  Static,
     // so its LDS base folds into the read addresses.  The (bin, dlt) list of
     // K float4 entries is dynamic LDS.
@@ -521,15 +531,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 
         // 4. greedy iterations.
         constexpr int NJ = PAIRS ? 9 : 16;   // registers in the loop
+        double pf[PRIOR ? 16 : 1];            // frequency prior of the lane's bins
+        if constexpr (PRIOR) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) pf[j] = tab->prior[(j + 16 * h) * 32 + c];
+        }
         double lbe = -1.0;   // packed local maximum
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            lbe = max_f64(lbe, pack_energy(fma(Rr[j], Rr[j], Ri[j] * Ri[j]), (uint32_t)(31 - 16 * h - j)));
+        for (int j = 0; j < NJ; ++j) {
+            double e = fma(Rr[j], Rr[j], Ri[j] * Ri[j]);
+            if constexpr (PRIOR) e *= pf[j];
+            lbe = max_f64(lbe, pack_energy(e, (uint32_t)(31 - 16 * h - j)));
+        }
         const uint8_t* Tb = smem;
         const uint32_t c16 = (uint32_t)c << 4, h13 = (uint32_t)h << 13;
+        int kdone = K;        // iterations run (fewer after an early stop)
+        double stop_at = 0.0;
         for (int it = 0; it < K; ++it) {
             int owner;
-            const uint32_t mlo = wave_argmax_packed(lbe, owner);
+            uint32_t mhi;
+            const uint32_t mlo = wave_argmax_packed(lbe, owner, mhi);
+            if constexpr (STOP) {   // wave-uniform: the packed maximum itself
+                const double eb = __hiloint2double((int)mhi, (int)mlo);
+                if (it == 0) {
+                    stop_at = stop_ratio * eb;
+                } else if (eb < stop_at) {
+                    kdone = it;
+                    break;
+                }
+            }
             const int b1 = 31 - (int)(mlo & 31u);
             const int b2 = owner & 31;
             const int jb = b1 & 15;
@@ -562,7 +592,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
                     xi = fma(-di, wv.x, xi);
                     Rr[j] = xr;
                     Ri[j] = xi;
-                    lbe = max_f64(lbe, pack_energy(fma(xr, xr, xi * xi), (uint32_t)(31 - 16 * h - j)));
+                    double e = fma(xr, xr, xi * xi);
+                    if constexpr (PRIOR) e *= pf[j];
+                    lbe = max_f64(lbe, pack_energy(e, (uint32_t)(31 - 16 * h - j)));
                 }
             } else {
                 const uint32_t Lp = ((c16 + (uint32_t)b2 * 16u) & 0x1F0u) | h13;
@@ -594,7 +626,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         const int p = lane & 15, q = lane >> 4;
         const int pm = 14 + (p >> 2), pn = 14 + (p & 3);
         double gr = 0.0;
-        for (int it = q; it < K; it += 4) {
+        for (int it = q; it < kdone; it += 4) {
             const float4 e = list[it];
             const uint32_t bf = __float_as_uint(e.x);
             const int t = ((int)(bf >> 5) * pm + (int)(bf & 31) * pn) & 31;
@@ -618,8 +650,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     }
 }
 
-hipError_t launch_fsr_tables(FsrTables* t, double rho, hipStream_t s) {
-    hipLaunchKernelGGL(fsr_tables_kernel, dim3(4), dim3(256), 0, s, t, rho);
+hipError_t launch_fsr_tables(FsrTables* t, double rho, double prior_sigma, hipStream_t s) {
+    hipLaunchKernelGGL(fsr_tables_kernel, dim3(4), dim3(256), 0, s, t, rho, prior_sigma);
     return hipGetLastError();
 }
 
@@ -630,8 +662,13 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
     const bool conc = p.concealed_weight > 0.0;
     if (conc && js.n != 0 && !host_frames) return hipErrorInvalidValue;
     if (conc && p.pairs) return hipErrorInvalidValue;     // not combined
+    const int opt = (p.prior_sigma > 0.0 ? 1 : 0) | (p.stop_ratio > 0.0 ? 2 : 0);
+    if (opt && (conc || p.pairs || p.precision != RFSR_PREC_FP64)) return hipErrorInvalidValue;
     auto kernel = fsr_block_kernel<RFSR_PREC_FP64, false, false>;
-    if (p.pairs) {
+    if (opt == 1) kernel = fsr_block_kernel<RFSR_PREC_FP64, false, false, 1>;
+    else if (opt == 2) kernel = fsr_block_kernel<RFSR_PREC_FP64, false, false, 2>;
+    else if (opt == 3) kernel = fsr_block_kernel<RFSR_PREC_FP64, false, false, 3>;
+    else if (p.pairs) {
         kernel = fsr_block_kernel<RFSR_PREC_FP64, false, true>;
         if (p.precision == RFSR_PREC_BF16X3) kernel = fsr_block_kernel<RFSR_PREC_BF16X3, false, true>;
         else if (p.precision == RFSR_PREC_FP16X3) kernel = fsr_block_kernel<RFSR_PREC_FP16X3, false, true>;
@@ -645,7 +682,7 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
     }
     if (!conc) {
         hipLaunchKernelGGL(kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
-                           p.gamma, p.proj_weight, p.overwrite, 0.0, 0, 0);
+                           p.gamma, p.proj_weight, p.overwrite, 0.0, 0, 0, p.stop_ratio);
         return hipGetLastError();
     }
     // wavefront: step t holds the blocks with 5 bi + bj = t of every frame
@@ -663,7 +700,7 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
         }
         if (grid == 0) continue;
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
-                           p.gamma, p.proj_weight, p.overwrite, p.concealed_weight, t, lo0);
+                           p.gamma, p.proj_weight, p.overwrite, p.concealed_weight, t, lo0, 0.0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(R):
     lib = R.lib()
     for n in declared_functions():
         assert hasattr(lib, n), n
-    assert lib.rfsr_version() == 10500
+    assert lib.rfsr_version() == 10600
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.rfsr_status_string(code).startswith(b"RFSR_")
 
@@ -82,7 +82,11 @@ def test_fsr_blocks_rejects_bad_arguments(R):
     fake = ctypes.c_void_p(4096)
     for kw, code in (({"iters": -1}, -1), ({"iters": 5000}, -1), ({"rho": 0.0}, -1), ({"rho": 1.5}, -1),
                      ({"gamma": 0.0}, -1), ({"gamma": 2.0}, -1), ({"proj_weight": -1.0}, -1),
-                     ({"block": 8}, -5), ({"support": 16}, -5)):
+                     ({"block": 8}, -5), ({"support": 16}, -5),
+                     ({"prior_sigma": -0.1}, -1), ({"prior_sigma": 1.5}, -1), ({"stop_ratio": -1.0}, -1),
+                     ({"stop_ratio": 1.0}, -1), ({"prior_sigma": 0.8, "pairs": True}, -5),
+                     ({"stop_ratio": 0.01, "precision": "bf16x3"}, -5),
+                     ({"prior_sigma": 0.8, "concealed_weight": 0.5}, -5)):
         p = R.FSRParams(**kw)
         c = p.c()
         assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == code, kw
