@@ -35,7 +35,8 @@ METHODS = [
 ]
 
 
-def run(sequences, method, kind_masks, R, torch, dev, search=9, iters=100, precision="fp64", concealed=0.0):
+def run(sequences, method, kind_masks, R, torch, dev, search=9, iters=100, precision="fp64", concealed=0.0,
+        prior=0.0, stop=0.0):
     """Per-frame (psnr, ssim) arrays (n_seq, T) of one method on the given
     sequences (uint8 frames (T, H, W) each) with their masks."""
     import numpy as np
@@ -43,7 +44,8 @@ def run(sequences, method, kind_masks, R, torch, dev, search=9, iters=100, preci
     T = sequences[0].shape[0]
     sizes = [tuple(f.shape[1:]) for f in sequences]
     me = R.MEParams(search=search, check=check if nref else "none")
-    fsr = R.FSRParams(iters=iters, overwrite=overwrite, precision=precision, concealed_weight=concealed)
+    fsr = R.FSRParams(iters=iters, overwrite=overwrite, precision=precision, concealed_weight=concealed,
+                      prior_sigma=prior, stop_ratio=stop)
     ss = R.StreamSet(sizes, me, fsr, nref=nref, graphs=True, device=dev)
     gt = [[torch.from_numpy(f[t]).to(dev) for t in range(T)] for f in sequences]
     meas = [[torch.from_numpy(f[t] * m[t]).to(dev) for t in range(T)] for f, m in zip(sequences, kind_masks)]
@@ -66,6 +68,8 @@ def main(argv=None):
     ap.add_argument("--search", type=int, default=9)
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--concealed", type=float, default=0.0, help="concealed weighting delta")
+    ap.add_argument("--prior", type=float, default=0.0, help="FSR frequency-weighting prior sigma (0: off)")
+    ap.add_argument("--stop", type=float, default=0.0, help="FSR residual-energy early-stop ratio (0: off)")
     a = ap.parse_args(argv)
 
     import numpy as np
@@ -95,12 +99,13 @@ def main(argv=None):
 
     out = {"study": "quality grid on synthetic video (Tables 1-2 / Fig. 4 analogue)", "size": f"{W}x{H}",
            "frames": a.frames, "sequences": a.sequences, "iters": a.iters, "search": a.search,
-           "precision": a.precision, "concealed": a.concealed, "results": {}}
+           "precision": a.precision, "concealed": a.concealed, "prior": a.prior, "stop": a.stop, "results": {}}
     for kind in ("fixed", "dynamic"):
         base = None
         for method in METHODS:
             t1 = time.perf_counter()
-            p, s = run(seqs, method, masks[kind], R, torch, dev, a.search, a.iters, a.precision, a.concealed)
+            p, s = run(seqs, method, masks[kind], R, torch, dev, a.search, a.iters, a.precision, a.concealed,
+                       a.prior, a.stop)
             if method[0] == "FSR":
                 base = p
             gain = (p - base).mean(axis=0)
