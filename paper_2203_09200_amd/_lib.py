@@ -427,9 +427,9 @@ class Sequence:
     runs (it starts once frame t-1's projection is done, so that it does
     not compete with frame t-1's own motion path), and only the lag-1
     reference, the projection and FSR (rfsr_frame_finish) wait for frame
-    t-1.  Two workspaces alternate between frames.  The inputs of push() must be complete on the device
-    when push() is called (pass `ready`, an event, if they are still being
-    produced)."""
+    t-1.  Two workspaces alternate between frames.  The inputs of push()
+    must be complete on the device when push() is called (pass `ready`, a
+    torch event, if they are still being produced)."""
 
     def __init__(self, H, W, me: MEParams | None = None, fsr: FSRParams | None = None,
                  nref=3, device=None, pipelined=False):
