@@ -232,8 +232,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
 
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
-              "(streams shard across GPUs without communication, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {a.gpus} is not supported "
+              "(independent streams would shard across GPUs without communication)", file=sys.stderr)
         return 2
 
     import numpy as np
