@@ -40,7 +40,7 @@ typedef enum {
     RFSR_ESHAPE = -2,        /* H, W or pitch not supported                     */
     RFSR_EWORKSPACE = -3,    /* workspace null, too small or misaligned         */
     RFSR_EDEVICE = -4,       /* HIP runtime error (no device, launch failure)   */
-    RFSR_EUNSUPPORTED = -5   /* valid request this build does not implement     */
+    RFSR_EUNSUPPORTED = -5   /* valid request this library does not implement   */
 } rfsr_status;
 
 /* Consistency check applied to the forward motion field.
@@ -76,7 +76,7 @@ typedef enum { RFSR_DFSR = 0, RFSR_RFSR = 1 } rfsr_overwrite;
  * total order (S, |v|_1, raster index of v).  Reverse costs are compared
  * normalised by the number of measured template pixels. */
 typedef struct {
-    int32_t tmpl;        /* template size; this build supports 4             */
+    int32_t tmpl;        /* template size; the library supports 4           */
     int32_t search;      /* search radius R, 0..15                            */
     int32_t check;       /* rfsr_check                                        */
     int32_t rmc_radius;  /* RMC radius, 0..15; 0 selects `search`             */
@@ -93,8 +93,8 @@ typedef struct {
  * CDNA4 vector ALU); float32 drifts past the 1e-3 output tolerance within
  * 100 iterations. */
 typedef struct {
-    int32_t block;       /* B; this build supports 4                          */
-    int32_t support;     /* M; this build supports 32                         */
+    int32_t block;       /* B; the library supports 4                        */
+    int32_t support;     /* M; the library supports 32                       */
     int32_t iters;       /* K, 0..1024                                        */
     int32_t overwrite;   /* rfsr_overwrite                                    */
     double rho;          /* 0 < rho <= 1                                      */

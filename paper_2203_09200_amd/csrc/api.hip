@@ -694,7 +694,7 @@ const char* rfsr_status_string(int32_t status) {
         case RFSR_ESHAPE: return "RFSR_ESHAPE: unsupported H, W or pitch";
         case RFSR_EWORKSPACE: return "RFSR_EWORKSPACE: workspace null, misaligned or too small";
         case RFSR_EDEVICE: return "RFSR_EDEVICE: HIP runtime error";
-        case RFSR_EUNSUPPORTED: return "RFSR_EUNSUPPORTED: parameters not supported by this build";
+        case RFSR_EUNSUPPORTED: return "RFSR_EUNSUPPORTED: parameters not supported by this library";
         default: return "unknown rfsr status";
     }
 }
