@@ -86,3 +86,23 @@ def test_fsr_options_1080p_sampled_blocks():
     amb = gaps < TAU_FP32
     print(f"1080p prior + stop: max {d[~amb].max():.2e} over {(~amb).sum()} blocks")
     assert d[~amb].max() <= FSR_TOL
+
+
+def test_fsr_options_in_a_batch_equal_single_frames():
+    """A batch of frames of different sizes with both options gives the
+    single-frame results bit for bit."""
+    R = need_gpu()
+    me, fsr = R.MEParams(search=6), R.FSRParams(iters=60, prior_sigma=0.9, stop_ratio=1e-4)
+    frames = []
+    for i, (H, W, nref) in enumerate([(64, 80, 3), (48, 64, 1), (32, 96, 0)]):
+        rng = np.random.default_rng(700 + i)
+        f, _ = synth.video_translate_edges(nref + 1, H, W, rng, max_step=2, n_edges=2)
+        m = synth.mask_sequence("dynamic", nref + 1, H, W, rng)
+        meas = synth.measured(f, m)
+        refs = tuple((dev(f[nref - 1 - k]), dev(meas[nref - 1 - k]), dev(m[nref - 1 - k])) for k in range(nref))
+        frames.append((dev(meas[nref]), dev(m[nref]), refs))
+    single = [tuple(host(x) for x in R.reconstruct_frame(c, mk, refs, me, fsr)) for c, mk, refs in frames]
+    b = R.Batch([R.BatchFrame(c, mk, refs, out_u8=torch.empty_like(c)) for c, mk, refs in frames], me, fsr)
+    got = [(host(o), host(u)) for o, u in b.run()]
+    for (o1, u1), (o2, u2) in zip(single, got):
+        assert np.array_equal(o1, o2) and np.array_equal(u1, u2)
