@@ -131,9 +131,11 @@ def test_frame_split_equals_whole(check):
         assert np.array_equal(host(o2), whole[0]) and np.array_equal(host(u2), whole[1]), first
 
 
-@pytest.mark.parametrize("H,W,T,check", [(64, 80, 7, "nnc_frmc"), (64, 80, 6, "rme"), (64, 80, 6, "rmc"),
-                                         (64, 80, 6, "frmc"), (64, 80, 6, "none"), (1080, 1920, 5, "nnc_frmc")])
-def test_pipelined_sequence_equals_plain(H, W, T, check):
+@pytest.mark.parametrize("H,W,T,check,nref", [(64, 80, 7, "nnc_frmc", 3), (64, 80, 6, "rme", 3),
+                                              (64, 80, 6, "rmc", 3), (64, 80, 6, "frmc", 3),
+                                              (64, 80, 6, "none", 3), (64, 80, 6, "nnc_frmc", 2),
+                                              (64, 80, 5, "nnc_frmc", 1), (1080, 1920, 5, "nnc_frmc", 3)])
+def test_pipelined_sequence_equals_plain(H, W, T, check, nref):
     """The pipelined recursion (early motion path of the lag >= 2 references
     on a side stream, overlapping the previous frame's FSR) reproduces the
     plain recursion bit for bit, frame by frame."""
@@ -146,7 +148,7 @@ def test_pipelined_sequence_equals_plain(H, W, T, check):
     me, fsr = R.MEParams(search=9, check=check), R.FSRParams(iters=100)
     res = []
     for pipelined in (False, True):
-        seq = R.Sequence(H, W, me, fsr, pipelined=pipelined)
+        seq = R.Sequence(H, W, me, fsr, nref=nref, pipelined=pipelined)
         outs = [seq.push(d_meas[t], d_mask[t]) for t in range(T)]
         torch.cuda.synchronize()
         res.append([(host(o), host(u)) for o, u in outs])
