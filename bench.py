@@ -68,19 +68,20 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def traffic_from_profile(kernel_src: str):
-    """HBM bytes per FSR launch from the committed PMC summary, or None when
-    the kernel source changed since the counters were taken."""
+def counters_from_profile(kernel_src: str):
+    """The committed PMC record of the FSR kernel (HBM bytes and VALU
+    wave-instructions per 1080p launch), or {} when the kernel source changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "fsr_block_kernel_1080p_traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as f:
         rec = json.load(f)
     with open(kernel_src, "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
     if rec.get("kernel_sha256") != digest:
-        return None
-    return rec.get("bytes_per_launch")
+        return {}
+    return rec
 
 
 def cpu_baseline(frames, masks, me_o, fsr_o, crop=176):
@@ -310,11 +311,22 @@ def main(argv=None):
     nblk = (H // 4) * (W // 4)
     flops = fsr_flops_per_block(a.iters, a.pairs) * nblk
     achieved = flops / fsr_avg_s / 1e12
-    traffic = traffic_from_profile(os.path.join(ROOT, "paper_2203_09200_amd", "csrc", "fsr.hip"))
+    rec = counters_from_profile(os.path.join(ROOT, "paper_2203_09200_amd", "csrc", "fsr.hip"))
+    default_fsr = not (a.pairs or a.concealed or a.prior or a.stop or a.precision != "fp64") and \
+        a.iters == 100 and (H, W) == (1080, 1920)
+    # the counters were taken on this kernel and workload only
+    traffic = rec.get("bytes_per_launch") if default_fsr else None
     roofline = {"kernel": "fsr_block_kernel", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4), "traffic": traffic,
                 "flops_per_launch": flops, "avg_launch_ms": round(fsr_avg_s * 1e3, 4)}
+    if default_fsr and rec.get("valu_insts_per_dispatch"):
+        # the same launch against the vector-ALU issue rate: one wave64 instruction per 4 cycles per SIMD
+        peak_issue = 256 * 4 * 2.4e9 / 4 / 1e9
+        got = rec["valu_insts_per_dispatch"] / fsr_avg_s / 1e9
+        roofline["issue"] = {"unit": "G wave-instr/s", "achieved": round(got, 2), "peak": peak_issue,
+                             "frac": round(got / peak_issue, 4),
+                             "valu_insts_per_launch": rec["valu_insts_per_dispatch"]}
     if a.stop:
         roofline["note"] = "flops counted for K iterations per block; the early stop runs fewer"
     if a.prior:

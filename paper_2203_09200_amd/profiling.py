@@ -12,7 +12,9 @@ WRITE_SIZE of the same run calibrate the counters' units.
 `record` writes profiles/fsr_block_kernel_1080p_traffic.json from the
 per-dispatch counter values read off the rocprofv3 CSVs, keyed by the
 SHA-256 of the kernel source, so that bench.py reports `traffic` only while
-the kernel is unchanged.
+the kernel is unchanged.  With --sq-csv (a run that collected SQ_INSTS_VALU)
+it also records the VALU wave-instructions per dispatch, from which bench.py
+reports the kernel's position against the vector-ALU issue rate.
 """
 from __future__ import annotations
 
@@ -70,7 +72,7 @@ def _counter_per_dispatch(csv_path: str, kernel_substr: str, counter: str):
     return vals
 
 
-def record(fsr_fetch_csv, fsr_write_csv, copy_fetch_csv, copy_write_csv, copy_mib, copy_kernel):
+def record(fsr_fetch_csv, fsr_write_csv, copy_fetch_csv, copy_write_csv, copy_mib, copy_kernel, sq_csv=None):
     ff = _counter_per_dispatch(fsr_fetch_csv, "fsr_block_kernel", "FETCH_SIZE")
     fw = _counter_per_dispatch(fsr_write_csv, "fsr_block_kernel", "WRITE_SIZE")
     cf = _counter_per_dispatch(copy_fetch_csv, copy_kernel, "FETCH_SIZE")
@@ -89,6 +91,10 @@ def record(fsr_fetch_csv, fsr_write_csv, copy_fetch_csv, copy_write_csv, copy_mi
            "copy_fetch_kib": max(cf), "copy_write_kib": max(cw),
            "fetch_scale_bytes_per_unit": s_fetch, "write_scale_bytes_per_unit": s_write,
            "bytes_per_launch": fetch_b + write_b}
+    if sq_csv:
+        vi = _counter_per_dispatch(sq_csv, "fsr_block_kernel", "SQ_INSTS_VALU")
+        if vi:
+            rec["valu_insts_per_dispatch"] = sum(vi) / len(vi)
     out = os.path.join(ROOT, "profiles", "fsr_block_kernel_1080p_traffic.json")
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
@@ -111,6 +117,7 @@ def main(argv=None):
     a3.add_argument("copy_write_csv")
     a3.add_argument("--copy-mib", type=int, default=1024)
     a3.add_argument("--copy-kernel", default="copyBuffer")
+    a3.add_argument("--sq-csv", default=None, help="counter CSV of a run with SQ_INSTS_VALU")
     a = ap.parse_args(argv)
     if a.cmd == "fsr":
         run_fsr(a.reps, a.delta, a.precision)
@@ -118,7 +125,7 @@ def main(argv=None):
         run_copy(a.mib)
     else:
         record(a.fsr_fetch_csv, a.fsr_write_csv, a.copy_fetch_csv, a.copy_write_csv, a.copy_mib,
-               a.copy_kernel)
+               a.copy_kernel, a.sq_csv)
     return 0
 
 
