@@ -408,6 +408,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     extern __shared__ float4 list[];
     uint8_t* smem = reinterpret_cast<uint8_t*>(s_T);
 
+    // The frame's critical path: where other kernels share the SIMD (the next
+    // frame's early motion path), the issue arbiter serves these waves first.
+    __builtin_amdgcn_s_setprio(3);
     const int lane = threadIdx.x;
     const int c = lane & 31, h = lane >> 5;
     const double* __restrict__ tw = tab->tw;
