@@ -22,7 +22,6 @@ oracle's throughput on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,6 +33,7 @@ if ROOT not in sys.path:
 
 # MI355X published peaks
 PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 
@@ -68,18 +68,17 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def counters_from_profile(kernel_src: str):
+def counters_from_profile():
     """The committed PMC record of the FSR kernel (HBM bytes and VALU
-    wave-instructions per 1080p launch), or {} when the kernel source changed
-    since the counters were taken."""
+    wave-instructions per 1080p launch), or {} when the kernel's sources
+    changed since the counters were taken."""
+    from paper_2203_09200_amd.profiling import kernel_digest
     path = os.path.join(ROOT, "profiles", "fsr_block_kernel_1080p_traffic.json")
     if not os.path.exists(path):
         return {}
     with open(path) as f:
         rec = json.load(f)
-    with open(kernel_src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("kernel_sha256") != digest:
+    if rec.get("kernel_sha256") != kernel_digest():
         return {}
     return rec
 
@@ -102,6 +101,39 @@ def cpu_baseline(frames, masks, me_o, fsr_o, crop=176):
             "kind": "oracle",
             "sample": f"one {crop}x{crop} crop of frame 3 (three references, reference "
                       f"frames = ground truth), single process; {dt:.1f} s"}
+
+
+def plain_fp32_form(a, seq_args, d_meas, d_mask, frames, ref_out, stream):
+    """The same recursion with every FSR step in float32 (one untimed and one
+    timed step of the sequence), beside the float64 headline: throughput,
+    PSNR, and the distance of its outputs from the float64 form's."""
+    import numpy as np
+    import torch
+    import paper_2203_09200_amd as R
+    H, W, me, dev = seq_args
+    F = len(d_meas)
+    fsr32 = R.FSRParams(iters=a.iters, precision="fp32")
+    seq = R.Sequence(H, W, me, fsr32, device=dev, pipelined=not a.no_pipeline)
+    outs = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(F)]
+
+    def step():
+        seq.reset()
+        for t in range(F):
+            seq.push(d_meas[t], d_mask[t], stream=stream, out=outs[t])
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    got = [o.cpu().numpy() for o in outs]
+    d = np.concatenate([np.abs(g.astype(np.float64) - r).ravel() for g, r in zip(got, ref_out)])
+    return {"value": round(F * H * W / dt / 1e6, 3), "unit": "HR Mpix/s", "ms_per_step": round(dt * 1e3, 3),
+            "psnr_db": round(float(np.mean([psnr(frames[t], got[t]) for t in range(F)])), 3),
+            "max_abs_vs_f64": round(float(d.max()), 4),
+            "frac_px_over_1e-3_vs_f64": round(float((d > 1e-3).mean()), 5),
+            "form": "FFT, table, residual and energies in float32 (precision fp32); one timed step"}
 
 
 def run_multistream(a, dev):
@@ -180,7 +212,8 @@ def run_multistream(a, dev):
         "n_gpus": 1, "steps": a.steps, "warmup": warm,
         "ms_per_step": round(elapsed / a.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else f"f64 (block DFT {a.precision}, float32 accumulate)",
+        "dtype": {"fp64": "f64", "fp32": "f32"}.get(a.precision,
+                                                     f"f64 (block DFT {a.precision}, float32 accumulate)"),
         "data": "synthetic (seeded smooth texture, 8x8 translating regions, 5% occluders) per stream",
         "config": {"workload": f"48 streams (16x352x288, 16x1280x720, 12x1920x1080, 4x3840x2160), "
                                f"{T} frames cycled, even streams fixed mask / odd dynamic, D-FSR + "
@@ -227,9 +260,11 @@ def main(argv=None):
                     help="concealed weighting delta (> 0: raster-order blocks as a wavefront)")
     ap.add_argument("--pairs", action="store_true",
                     help="real-valued FSR (a conjugate pair per iteration; use about half the iterations)")
-    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3"], default="fp64",
-                    help="block DFT arithmetic (float64 FFT, or matrix-core GEMMs with split "
-                         "16-bit operands); the FSR iterations are float64 in every case")
+    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3", "fp32"], default="fp64",
+                    help="FSR arithmetic: float64 (default); block DFT as matrix-core GEMMs with split "
+                         "16-bit operands and float64 iterations; or every step float32 (fp32)")
+    ap.add_argument("--no-fp32-form", action="store_true",
+                    help="skip the plain float32 form reported beside the float64 result")
     a = ap.parse_args(argv)
 
     if a.gpus != 1:
@@ -303,7 +338,8 @@ def main(argv=None):
             proj_ms.append(e[1].elapsed_ms(e[2]))
             fsr_ms.append(e[2].elapsed_ms(e[3]))
 
-    q = float(np.mean([psnr(frames[t], outs[t].cpu().numpy()) for t in range(F)]))
+    host_out = [outs[t].cpu().numpy() for t in range(F)]
+    q = float(np.mean([psnr(frames[t], host_out[t]) for t in range(F)]))
 
     npx = F * H * W
     value = npx * a.steps / elapsed / 1e6
@@ -311,14 +347,15 @@ def main(argv=None):
     nblk = (H // 4) * (W // 4)
     flops = fsr_flops_per_block(a.iters, a.pairs) * nblk
     achieved = flops / fsr_avg_s / 1e12
-    rec = counters_from_profile(os.path.join(ROOT, "paper_2203_09200_amd", "csrc", "fsr.hip"))
+    rec = counters_from_profile()
     default_fsr = not (a.pairs or a.concealed or a.prior or a.stop or a.precision != "fp64") and \
         a.iters == 100 and (H, W) == (1080, 1920)
     # the counters were taken on this kernel and workload only
     traffic = rec.get("bytes_per_launch") if default_fsr else None
-    roofline = {"kernel": "fsr_block_kernel", "bound": "alu", "achieved": round(achieved, 3),
-                "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4), "traffic": traffic,
+    peak = PEAK_FP32_VECTOR_TFLOPS if a.precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS
+    roofline = {"kernel": "fsr_block_kernel_f32" if a.precision == "fp32" else "fsr_block_kernel",
+                "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic,
                 "flops_per_launch": flops, "avg_launch_ms": round(fsr_avg_s * 1e3, 4)}
     if default_fsr and rec.get("valu_insts_per_dispatch"):
         # the same launch against the vector-ALU issue rate: one wave64 instruction per 4 cycles per SIMD
@@ -331,6 +368,11 @@ def main(argv=None):
         roofline["note"] = "flops counted for K iterations per block; the early stop runs fewer"
     if a.prior:
         roofline["note_prior"] = "the prior adds one multiply per bin and iteration, not counted"
+
+    fp32_form = None
+    if a.precision == "fp64" and not (a.pairs or a.concealed or a.prior or a.stop or a.no_fp32_form):
+        fp32_form = plain_fp32_form(a, seq_args=(H, W, me, dev), d_meas=d_meas, d_mask=d_mask, frames=frames,
+                                    ref_out=host_out, stream=stream)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -350,12 +392,14 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else f"f64 (block DFT {a.precision}, float32 accumulate)",
+        "dtype": {"fp64": "f64", "fp32": "f32"}.get(a.precision,
+                                                     f"f64 (block DFT {a.precision}, float32 accumulate)"),
         "data": "synthetic (seeded smooth texture, 8x8 translating regions, 5% occluders)",
         "config": {"workload": f"{W}x{H} uint8, {F} frames, dynamic quarter mask, D-FSR + "
                                f"{a.check.upper().replace('_', '+')}, R={a.search}, T=4, "
                                f"4x4 blocks, 32x32 support, rho=0.7, gamma=0.5, K={a.iters}, 3 references"
-                               + ("" if a.precision == "fp64" else f", block DFT {a.precision}")
+                               + {"fp64": "", "fp32": ", FSR all float32"}.get(a.precision,
+                                                                              f", block DFT {a.precision}")
                                + (", conjugate-pair FSR" if a.pairs else "")
                                + (f", concealed weighting {a.concealed}" if a.concealed else "")
                                + (f", frequency prior sigma {a.prior}" if a.prior else "")
@@ -374,6 +418,7 @@ def main(argv=None):
                                    "previous frame's FSR)" if not a.no_pipeline else "all references")},
         "psnr_db": round(q, 3),
         "roofline": roofline,
+        "fp32_form": fp32_form,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))

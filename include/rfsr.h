@@ -100,7 +100,7 @@ typedef struct {
     double rho;          /* 0 < rho <= 1                                      */
     double gamma;        /* 0 < gamma < 2                                     */
     double proj_weight;  /* >= 0, weight of projected samples                 */
-    int32_t precision;   /* rfsr_precision of the block DFT (0 = float64)     */
+    int32_t precision;   /* rfsr_precision (0 = float64)                      */
     int32_t pairs;       /* 0: complex single bins; 1: conjugate pairs        */
     double concealed_weight; /* delta, 0 <= delta <= 1 (0 = independent blocks) */
     double prior_sigma;  /* frequency-weighting prior, 0 (off) or 0 < sigma <= 1 */
@@ -140,20 +140,26 @@ typedef struct {
  * They run in a kernel of their own, so the default loop carries no test
  * for them. */
 
-/* Arithmetic of the block DFT that starts FSR (R = DFT(w s), W = DFT(w));
- * the iterations are float64 in every case.
+/* Arithmetic of FSR.  FP64, BF16X3 and FP16X3 select the block DFT that
+ * starts FSR (R = DFT(w s), W = DFT(w)) and keep the iterations in float64:
  *   FP64     float64 FFT on the vector ALU (the reference precision).
  *   BF16X3   two 32x32 GEMM stages on the matrix cores (MFMA), operands
  *            split as hi + lo in bfloat16, products hi*hi + hi*lo + lo*hi
  *            accumulated in float32.
  *   FP16X3   the same with float16 operands.
- * The 16-bit forms trade DFT accuracy (float32 accumulation, ~2^-16 / ~2^-22
- * operand splits) for matrix-core throughput; they are not bit-compatible
- * with FP64 and exist to quantify that trade. */
+ *   FP32     every step in float32: FFT, table, residual and energies (the
+ *            plain float32 form).  Complex single bins and independent
+ *            blocks only (pairs, concealed_weight > 0 and the literature
+ *            options give RFSR_EUNSUPPORTED).
+ * The forms other than FP64 trade accuracy (float32 accumulation, ~2^-16 /
+ * ~2^-22 operand splits, float32 rounding of the residual) for throughput;
+ * they are not bit-compatible with FP64 and are not held to its 1e-3 output
+ * tolerance: they exist to quantify that trade. */
 typedef enum {
     RFSR_PREC_FP64 = 0,
     RFSR_PREC_BF16X3 = 1,
-    RFSR_PREC_FP16X3 = 2
+    RFSR_PREC_FP16X3 = 2,
+    RFSR_PREC_FP32 = 3
 } rfsr_precision;
 
 /* Indices into the optional counters array of rfsr_motion_check. */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librfsr.so")
 
 CHECKS = {"none": 0, "rme": 1, "rmc": 2, "frmc": 3, "nnc": 4, "nnc_frmc": 5}
 OVERWRITE = {"dfsr": 0, "rfsr": 1}
-PRECISION = {"fp64": 0, "bf16x3": 1, "fp16x3": 2}
+PRECISION = {"fp64": 0, "bf16x3": 1, "fp16x3": 2, "fp32": 3}
 NCOUNTERS = 4
 COUNTER_NAMES = ("forward_costs", "check_costs", "checked_pixels", "accepted")
 
@@ -63,7 +63,7 @@ class FSRParams:
     overwrite: str = "dfsr"
     block: int = 4
     support: int = 32
-    precision: str = "fp64"     # block DFT: "fp64", "bf16x3" or "fp16x3" (matrix cores)
+    precision: str = "fp64"     # "fp64"; block DFT "bf16x3" or "fp16x3" (matrix cores); "fp32" (all float32)
     concealed_weight: float = 0.0   # delta > 0: raster-order blocks (wavefront), single frames only
     pairs: bool = False             # real-valued FSR: conjugate pairs per iteration
     prior_sigma: float = 0.0        # frequency-weighting prior (0: off)

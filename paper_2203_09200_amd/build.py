@@ -23,7 +23,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librfsr.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "fsr.hip", "motion.hip", "quality.hip"]
+SOURCES = ["api.hip", "fsr.hip", "fsr32.hip", "motion.hip", "quality.hip"]
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

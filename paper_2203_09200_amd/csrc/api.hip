@@ -14,7 +14,7 @@ using namespace rfsr;
 
 namespace {
 
-constexpr int32_t kVersion = 10600;   // 1.6.0
+constexpr int32_t kVersion = 10700;   // 1.7.0
 constexpr int kMaxBatch = 4096;
 
 rfsr_status from_hip(hipError_t e) { return e == hipSuccess ? RFSR_OK : RFSR_EDEVICE; }
@@ -44,12 +44,13 @@ rfsr_status check_fsr(const rfsr_fsr_params* p) {
     if (!(p->proj_weight >= 0.0) || !isfinite(p->proj_weight)) return RFSR_EINVAL;
     if (p->overwrite != RFSR_DFSR && p->overwrite != RFSR_RFSR) return RFSR_EINVAL;
     if (p->block < 1 || p->support < p->block) return RFSR_EINVAL;
-    if (p->precision < RFSR_PREC_FP64 || p->precision > RFSR_PREC_FP16X3) return RFSR_EINVAL;
+    if (p->precision < RFSR_PREC_FP64 || p->precision > RFSR_PREC_FP32) return RFSR_EINVAL;
     if (!(p->concealed_weight >= 0.0 && p->concealed_weight <= 1.0)) return RFSR_EINVAL;
     if (p->pairs != 0 && p->pairs != 1) return RFSR_EINVAL;
     if (!(p->prior_sigma >= 0.0 && p->prior_sigma <= 1.0)) return RFSR_EINVAL;
     if (!(p->stop_ratio >= 0.0 && p->stop_ratio < 1.0)) return RFSR_EINVAL;
     if (p->pairs && p->concealed_weight > 0.0) return RFSR_EUNSUPPORTED;
+    if (p->precision == RFSR_PREC_FP32 && (p->pairs || p->concealed_weight > 0.0)) return RFSR_EUNSUPPORTED;
     if ((p->prior_sigma > 0.0 || p->stop_ratio > 0.0) &&
         (p->pairs || p->concealed_weight > 0.0 || p->precision != RFSR_PREC_FP64))
         return RFSR_EUNSUPPORTED;

@@ -216,6 +216,9 @@ hipError_t launch_fsr_tables(FsrTables* t, double rho, double prior_sigma, hipSt
 // table (frame sizes for the wavefront grid).
 hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
                       const FsrTables* tables, hipStream_t s, const FrameJob* host_frames = nullptr);
+// The float32 form (precision RFSR_PREC_FP32; independent blocks, complex bins).
+hipError_t launch_fsr_f32(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
+                          const FsrTables* tables, hipStream_t s);
 
 // Window planes of the frames in `js` (frames with fm == nullptr skipped).
 hipError_t launch_windows(const Jobs<FrameJob>& js, int total_groups, hipStream_t s);

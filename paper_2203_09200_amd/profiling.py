@@ -11,8 +11,8 @@ WRITE_SIZE of the same run calibrate the counters' units.
 
 `record` writes profiles/fsr_block_kernel_1080p_traffic.json from the
 per-dispatch counter values read off the rocprofv3 CSVs, keyed by the
-SHA-256 of the kernel source, so that bench.py reports `traffic` only while
-the kernel is unchanged.  With --sq-csv (a run that collected SQ_INSTS_VALU)
+SHA-256 of the kernel's sources (KERNEL_SOURCES), so that bench.py reports
+`traffic` only while the kernel is unchanged.  With --sq-csv (a run that collected SQ_INSTS_VALU)
 it also records the VALU wave-instructions per dispatch, from which bench.py
 reports the kernel's position against the vector-ALU issue rate.
 """
@@ -27,6 +27,18 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
+
+# sources that compile into fsr_block_kernel
+KERNEL_SOURCES = ("fsr.hip", "fft.h", "common.h")
+
+
+def kernel_digest() -> str:
+    """SHA-256 over the FSR kernel's sources, in a fixed order."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def run_fsr(reps: int, delta: float = 0.0, precision: str = "fp64"):
@@ -73,8 +85,8 @@ def _counter_per_dispatch(csv_path: str, kernel_substr: str, counter: str):
 
 
 def record(fsr_fetch_csv, fsr_write_csv, copy_fetch_csv, copy_write_csv, copy_mib, copy_kernel, sq_csv=None):
-    ff = _counter_per_dispatch(fsr_fetch_csv, "fsr_block_kernel", "FETCH_SIZE")
-    fw = _counter_per_dispatch(fsr_write_csv, "fsr_block_kernel", "WRITE_SIZE")
+    ff = _counter_per_dispatch(fsr_fetch_csv, "fsr_block_kernel<", "FETCH_SIZE")
+    fw = _counter_per_dispatch(fsr_write_csv, "fsr_block_kernel<", "WRITE_SIZE")
     cf = _counter_per_dispatch(copy_fetch_csv, copy_kernel, "FETCH_SIZE")
     cw = _counter_per_dispatch(copy_write_csv, copy_kernel, "WRITE_SIZE")
     nbytes = copy_mib << 20
@@ -83,16 +95,14 @@ def record(fsr_fetch_csv, fsr_write_csv, copy_fetch_csv, copy_write_csv, copy_mi
     s_write = nbytes / max(cw) if cw else None
     fetch_b = sum(ff) / len(ff) * s_fetch
     write_b = sum(fw) / len(fw) * s_write
-    with open(os.path.join(HERE, "csrc", "fsr.hip"), "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
     rec = {"kernel": "fsr_block_kernel", "workload": "1920x1080 frame, dynamic mask, K=100",
-           "kernel_sha256": digest, "fetch_kib_per_dispatch": sum(ff) / len(ff),
+           "kernel_sources": list(KERNEL_SOURCES), "kernel_sha256": kernel_digest(), "fetch_kib_per_dispatch": sum(ff) / len(ff),
            "write_kib_per_dispatch": sum(fw) / len(fw), "copy_mib": copy_mib,
            "copy_fetch_kib": max(cf), "copy_write_kib": max(cw),
            "fetch_scale_bytes_per_unit": s_fetch, "write_scale_bytes_per_unit": s_write,
            "bytes_per_launch": fetch_b + write_b}
     if sq_csv:
-        vi = _counter_per_dispatch(sq_csv, "fsr_block_kernel", "SQ_INSTS_VALU")
+        vi = _counter_per_dispatch(sq_csv, "fsr_block_kernel<", "SQ_INSTS_VALU")
         if vi:
             rec["valu_insts_per_dispatch"] = sum(vi) / len(vi)
     out = os.path.join(ROOT, "profiles", "fsr_block_kernel_1080p_traffic.json")

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(R):
     lib = R.lib()
     for n in declared_functions():
         assert hasattr(lib, n), n
-    assert lib.rfsr_version() == 10600
+    assert lib.rfsr_version() == 10700
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.rfsr_status_string(code).startswith(b"RFSR_")
 
@@ -86,10 +86,17 @@ def test_fsr_blocks_rejects_bad_arguments(R):
                      ({"prior_sigma": -0.1}, -1), ({"prior_sigma": 1.5}, -1), ({"stop_ratio": -1.0}, -1),
                      ({"stop_ratio": 1.0}, -1), ({"prior_sigma": 0.8, "pairs": True}, -5),
                      ({"stop_ratio": 0.01, "precision": "bf16x3"}, -5),
-                     ({"prior_sigma": 0.8, "concealed_weight": 0.5}, -5)):
+                     ({"prior_sigma": 0.8, "concealed_weight": 0.5}, -5),
+                     ({"precision": "fp32", "pairs": True}, -5),
+                     ({"precision": "fp32", "concealed_weight": 0.5}, -5),
+                     ({"precision": "fp32", "prior_sigma": 0.8}, -5),
+                     ({"precision": "fp32", "stop_ratio": 0.01}, -5)):
         p = R.FSRParams(**kw)
         c = p.c()
         assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == code, kw
+    c = R.FSRParams().c()
+    c.precision = 4
+    assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == -1
     c = R.FSRParams().c()
     c.overwrite = 7
     assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == -1

@@ -3,7 +3,8 @@ two 32x32 GEMM stages in bfloat16 / float16 split operands (hi*hi + hi*lo +
 lo*hi, float32 accumulation) against the float64 FFT path and the float64
 oracle, at 100 and 300 iterations, on the 3840x2160 workload (seeded sample
 of blocks) and on a full 128x128 frame (PSNR).  The iterations are float64 in
-every variant, so the differences measure the DFT alone."""
+every variant, so the differences measure the DFT alone.  The plain float32
+form (every step float32) is measured beside them."""
 import numpy as np
 import pytest
 import torch
@@ -14,7 +15,7 @@ from _gpu import FSR_TOL, TAU_FP32, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ("fp64", "bf16x3", "fp16x3")
+PRECS = ("fp64", "bf16x3", "fp16x3", "fp32")
 
 
 def block_errors(out, ora, blocks):
