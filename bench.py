@@ -104,16 +104,18 @@ def cpu_baseline(frames, masks, me_o, fsr_o, crop=176):
 
 
 def plain_fp32_form(a, seq_args, d_meas, d_mask, frames, ref_out, stream):
-    """The same recursion with every FSR step in float32 (one untimed and one
-    timed step of the sequence), beside the float64 headline: throughput,
-    PSNR, and the distance of its outputs from the float64 form's."""
+    """The plain float32 form beside the float64 headline: the same recursion,
+    one frame at a time (no overlap of consecutive frames, no graphs), every
+    FSR step in float32; one untimed and one timed step of the sequence.
+    Reports throughput, PSNR and the distance of its outputs from the float64
+    form's."""
     import numpy as np
     import torch
     import paper_2203_09200_amd as R
     H, W, me, dev = seq_args
     F = len(d_meas)
     fsr32 = R.FSRParams(iters=a.iters, precision="fp32")
-    seq = R.Sequence(H, W, me, fsr32, device=dev, pipelined=not a.no_pipeline)
+    seq = R.Sequence(H, W, me, fsr32, device=dev, pipelined=False)
     outs = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(F)]
 
     def step():
@@ -133,7 +135,8 @@ def plain_fp32_form(a, seq_args, d_meas, d_mask, frames, ref_out, stream):
             "psnr_db": round(float(np.mean([psnr(frames[t], got[t]) for t in range(F)])), 3),
             "max_abs_vs_f64": round(float(d.max()), 4),
             "frac_px_over_1e-3_vs_f64": round(float((d > 1e-3).mean()), 5),
-            "form": "FFT, table, residual and energies in float32 (precision fp32); one timed step"}
+            "form": "single stream, one frame at a time, FFT, table, residual and energies in float32 "
+                    "(precision fp32); one timed step"}
 
 
 def run_multistream(a, dev):

@@ -29,7 +29,8 @@ what-if runs on a CPU.
 
 prints one JSON line: offered load, sustained HR Mpix/s, p50/p99 latency
 (arrival -> result ready on the device), for the batched server and for the
-plain single-stream loop on the same request trace.
+plain single-stream loops (float64 FSR, and every FSR step in float32) on the
+same request trace.
 """
 from __future__ import annotations
 
@@ -482,8 +483,8 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--pool", type=int, default=8, help="distinct synthetic frames per size and mask kind")
-    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3"], default="fp64",
-                    help="block DFT arithmetic of the batched server (the plain loop stays fp64)")
+    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3", "fp32"], default="fp64",
+                    help="FSR arithmetic of the batched server (the plain loops are fp64 and fp32)")
     a = ap.parse_args(argv)
 
     import numpy as np
@@ -526,6 +527,7 @@ def main(argv=None):
     modes = [("batched", "batch", a.max_batch, a.max_inflight, a.precision)]
     if not a.no_plain:
         modes.append(("plain", "frame", 1, 1, "fp64"))
+        modes.append(("plain_fp32", "frame", 1, 1, "fp32"))
     budget = int(a.budget_gib * 2**30)
     for name, mode, mb, mi, prec in modes:
         fsr = R.FSRParams(iters=a.iters, precision=prec)
