@@ -46,49 +46,11 @@ __device__ __forceinline__ double max_f64(double a, double b) {
     return r;
 }
 
-// Row permutation of a double with DPP; every lane reads a valid source lane
-// for the patterns used here, so no 'old' value needs initialising.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-    return __hiloint2double((int)hi, (int)lo);
-}
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-// Maximum of non-negative doubles over the 64 lanes, left in every lane:
-// butterfly inside each 16-lane row with DPP, then across rows with the gfx950
-// permlane swaps (odd rows <-> even rows, upper half <-> lower half).
-__device__ __forceinline__ double pair_max(double v, int which) {
-    const uint64_t u = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
-    uint32_t a_lo, a_hi, b_lo, b_hi;
-    if (which == 16) {
-        const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-        a_lo = pl[0]; b_lo = pl[1]; a_hi = ph[0]; b_hi = ph[1];
-    } else {
-        const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-        const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-        a_lo = pl[0]; b_lo = pl[1]; a_hi = ph[0]; b_hi = ph[1];
-    }
-    const double a = __longlong_as_double((long long)(((uint64_t)a_hi << 32) | a_lo));
-    const double b = __longlong_as_double((long long)(((uint64_t)b_hi << 32) | b_lo));
-    return max_f64(a, b);
-}
-
-__device__ __forceinline__ double wave_allmax_f64(double v) {
-    v = max_f64(v, dpp_f64<kDppQuadXor1>(v));
-    v = max_f64(v, dpp_f64<kDppQuadXor2>(v));
-    v = max_f64(v, dpp_f64<kDppRowHalfMirror>(v));
-    v = max_f64(v, dpp_f64<kDppRowMirror>(v));
-    v = pair_max(v, 16);
-    return pair_max(v, 32);
 }
 
 // Argmax over the wave of non-negative packed energies (their bit patterns

@@ -7,7 +7,6 @@ pipelined), on sampled pixels and blocks the oracle recomputes one by one
 from the same inputs."""
 import numpy as np
 import pytest
-import torch
 
 import oracle as O
 import synth
