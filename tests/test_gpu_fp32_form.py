@@ -103,3 +103,47 @@ def test_fp32_form_in_frame_path_and_batch():
     c, mk, _ = frames[2]
     o3 = host(R.fsr_blocks(c.to(torch.float32), mk, fsr)[0])
     assert np.array_equal(o3, single[2][0])
+
+
+@pytest.mark.parametrize("H,W", [(4, 4), (16, 16384), (16384, 12)])
+def test_fp32_form_extreme_shapes(H, W):
+    """Smallest frame and maximum-length strips: K = 0 keeps exactly the
+    measured samples (as the float64 kernel does); K = 1 follows the oracle's
+    first pick to float32 rounding at sampled blocks."""
+    R = need_gpu()
+    rng = np.random.default_rng(H * 7 + W)
+    f = np.clip(128 + 40 * synth.bandlimited_noise(H, W, 2.0, rng), 0, 255).astype(np.uint8)
+    m = synth.fixed_mask(H, W, rng)
+    vals = (f * m).astype(np.float64)
+    v_d, m_d = dev(vals, torch.float32), dev(m)
+    o32 = host(R.fsr_blocks(v_d, m_d, R.FSRParams(iters=0, precision="fp32"))[0])
+    o64 = host(R.fsr_blocks(v_d, m_d, R.FSRParams(iters=0))[0])
+    assert np.array_equal(o32, o64) and np.array_equal(o32, vals.astype(np.float32))
+    out = host(R.fsr_blocks(v_d, m_d, R.FSRParams(iters=1, precision="fp32"))[0])
+    nbh, nbw = H // 4, W // 4
+    idx = rng.choice(nbh * nbw, size=min(32, nbh * nbw), replace=False)
+    blocks = np.stack([idx // nbw, idx % nbw], axis=1)
+    ora, gaps = O.fsr.fsr_blocks_out(vals, m, blocks, K=1)
+    got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
+    d = np.abs(got - ora).max(axis=(1, 2))
+    amb = gaps < TAU_FP32
+    assert np.isfinite(out).all()
+    if (~amb).any():
+        assert d[~amb].max() <= 5e-3
+
+
+def test_fp32_form_all_unknown_and_maximum_iterations():
+    """No samples: the model is zero.  K = 1024 (the largest list the LDS
+    holds) runs and stays finite and close to the float64 kernel's PSNR."""
+    R = need_gpu()
+    z = torch.zeros((32, 48), dtype=torch.float32, device="cuda")
+    c = torch.zeros((32, 48), dtype=torch.uint8, device="cuda")
+    out, u8 = R.fsr_blocks(z, c, R.FSRParams(iters=20, precision="fp32"))
+    assert (host(out) == 0).all() and (host(u8) == 0).all()
+    f, m, meas = frame(44, 64, 64)
+    v_d, m_d = dev(meas, torch.float32), dev(m)
+    o32 = host(R.fsr_blocks(v_d, m_d, R.FSRParams(iters=1024, precision="fp32"))[0])
+    o64 = host(R.fsr_blocks(v_d, m_d, R.FSRParams(iters=1024))[0])
+    assert np.isfinite(o32).all()
+    print(f"K=1024: PSNR fp32 {O.psnr(f, o32, 8):.3f}, fp64 {O.psnr(f, o64, 8):.3f}")
+    assert abs(O.psnr(f, o32, 8) - O.psnr(f, o64, 8)) < 0.5
