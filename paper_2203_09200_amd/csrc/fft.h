@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 namespace rfsr {
 
@@ -55,28 +56,49 @@ __device__ __forceinline__ void fft16(T (&re)[16], T (&im)[16], const T* __restr
     }
 }
 
+// Exchange the upper 32 lanes of a with the lower 32 lanes of b (gfx950
+// v_permlane32_swap, one per dword): afterwards a holds (a_lower, b_lower)
+// and b holds (a_upper, b_upper) over lanes (0-31, 32-63).
+__device__ __forceinline__ void swap_halves(float& a, float& b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap_halves(double& a, double& b) {
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)__double2loint(a), (uint32_t)__double2loint(b),
+                                                     false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)__double2hiint(a), (uint32_t)__double2hiint(b),
+                                                     false, false);
+    a = __hiloint2double((int)hi[0], (int)lo[0]);
+    b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
 // 32-point forward DFT of x[m], m = i + 16 h held by the lane pair (h=0, h=1)
 // at register i.  Afterwards register k' of lane h holds X[2 k' + h].
+// The radix-2 step pairs x[m] with x[m + 16]: swapping the lane halves of
+// registers i and i + 8 brings x[i], x[i + 16] into the lower lanes and
+// x[i + 8], x[i + 24] into the upper ones, the butterfly runs in registers,
+// and the same swap puts the sums back in the lower lanes and the twiddled
+// differences in the upper lanes.
 template <typename T>
 __device__ __forceinline__ void fft32_pair(T (&re)[16], T (&im)[16], int h, const T* __restrict__ tw) {
-    const T sgn = h ? T(-1) : T(1);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const T pr = __shfl_xor(re[i], 32);
-        const T pi = __shfl_xor(im[i], 32);
-        // h = 0: x[i] + x[i+16];  h = 1: (x[i] - x[i+16]) * w32^i
-        const T ur = fma(sgn, re[i], pr);
-        const T ui = fma(sgn, im[i], pi);
-        if (i == 0) {
-            re[i] = ur;
-            im[i] = ui;
-        } else {
-            const T twr = tw[2 * i], twi = tw[2 * i + 1];   // uniform loads, then select
-            const T cr = h ? twr : T(1);
-            const T ci = h ? twi : T(0);
-            re[i] = ur * cr - ui * ci;
-            im[i] = ur * ci + ui * cr;
-        }
+    for (int i = 0; i < 8; ++i) {
+        swap_halves(re[i], re[i + 8]);
+        swap_halves(im[i], im[i + 8]);
+        const T ar = re[i], ai = im[i], br = re[i + 8], bi = im[i + 8];
+        const T dr = ar - br, di = ai - bi;
+        re[i] = ar + br;
+        im[i] = ai + bi;
+        // twiddle w32^i for the pair in the lower lanes, w32^(i+8) in the upper ones
+        const T c0 = tw[2 * i], s0 = tw[2 * i + 1];          // uniform loads, then select
+        const T c1 = tw[2 * i + 16], s1 = tw[2 * i + 17];
+        const T cr = h ? c1 : c0;
+        const T ci = h ? s1 : s0;
+        re[i + 8] = fma(-di, ci, dr * cr);
+        im[i + 8] = fma(di, cr, dr * ci);
+        swap_halves(re[i], re[i + 8]);
+        swap_halves(im[i], im[i + 8]);
     }
     fft16(re, im, tw);
 }

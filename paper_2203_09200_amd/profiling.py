@@ -1,11 +1,11 @@
 """Small drivers to run under rocprofv3 (counter and trace collection).
 
-    python -m paper_2203_09200_amd.profiling fsr  [--reps 3] [--delta D] [--precision P]
+    python -m paper_2203_09200_amd.profiling fsr  [--reps 3] [--delta D] [--precision P] [--iters K ...]
                                                                # FSR kernel, 1080p workload frame
     python -m paper_2203_09200_amd.profiling copy [--mib 1024] # plain device copy of known size
 
 `fsr` launches fsr_blocks on one frame of the 1920x1080 benchmark workload
-(dynamic mask, K = 100) `reps` times.  `copy` copies a buffer of the given
+(dynamic mask, K = 100 or the given iteration counts) `reps` times each.  `copy` copies a buffer of the given
 size once with torch (reads and writes exactly `mib` MiB), so FETCH_SIZE and
 WRITE_SIZE of the same run calibrate the counters' units.
 
@@ -41,7 +41,7 @@ def kernel_digest() -> str:
     return h.hexdigest()
 
 
-def run_fsr(reps: int, delta: float = 0.0, precision: str = "fp64"):
+def run_fsr(reps: int, delta: float = 0.0, precision: str = "fp64", iters=(100,)):
     import numpy as np
     import torch
     sys.path.insert(0, ROOT)
@@ -51,16 +51,17 @@ def run_fsr(reps: int, delta: float = 0.0, precision: str = "fp64"):
     meas = synth.measured(f, m)[0]
     v = torch.from_numpy(meas.astype(np.float32)).cuda()
     c = torch.from_numpy(m[0]).cuda()
-    prm = R.FSRParams(iters=100, concealed_weight=delta, precision=precision)
-    R.fsr_blocks(v, c, prm)
-    torch.cuda.synchronize()
-    e0, e1 = R.Event(), R.Event()
-    e0.record()
-    for _ in range(reps):
+    for K in iters:
+        prm = R.FSRParams(iters=K, concealed_weight=delta, precision=precision)
         R.fsr_blocks(v, c, prm)
-    e1.record()
-    print(f"fsr_blocks x{reps} done: {e0.elapsed_ms(e1) / reps:.3f} ms per 1080p frame "
-          f"(delta {delta}, precision {precision})", flush=True)
+        torch.cuda.synchronize()
+        e0, e1 = R.Event(), R.Event()
+        e0.record()
+        for _ in range(reps):
+            R.fsr_blocks(v, c, prm)
+        e1.record()
+        print(f"fsr_blocks x{reps} done: {e0.elapsed_ms(e1) / reps:.3f} ms per 1080p frame "
+              f"(K {K}, delta {delta}, precision {precision})", flush=True)
 
 
 def run_copy(mib: int):
@@ -118,6 +119,8 @@ def main(argv=None):
     a1.add_argument("--reps", type=int, default=3)
     a1.add_argument("--delta", type=float, default=0.0, help="concealed weighting")
     a1.add_argument("--precision", default="fp64")
+    a1.add_argument("--iters", type=int, nargs="+", default=[100],
+                    help="iteration counts to time in turn (K = 0 times the setup alone)")
     a2 = sub.add_parser("copy")
     a2.add_argument("--mib", type=int, default=1024)
     a3 = sub.add_parser("record")
@@ -130,7 +133,7 @@ def main(argv=None):
     a3.add_argument("--sq-csv", default=None, help="counter CSV of a run with SQ_INSTS_VALU")
     a = ap.parse_args(argv)
     if a.cmd == "fsr":
-        run_fsr(a.reps, a.delta, a.precision)
+        run_fsr(a.reps, a.delta, a.precision, a.iters)
     elif a.cmd == "copy":
         run_copy(a.mib)
     else:
