@@ -14,7 +14,10 @@ Modules
   me          Sec. 2.2: pixel-wise template-matching motion estimation.
   checks      Sec. 2.2 (RME), Sec. 3.1.1 (RMC, FRMC), Sec. 3.1.2 / Eq. (1) (NNC).
   projection  Sec. 2.2: projection of measured past pixels, averaged.
-  fsr         Sec. 2.1 / Sec. 3.2: block-wise FSR with concealed weighting 0.
+  fsr         Sec. 2.1 / Sec. 3.2: block-wise FSR with concealed weighting 0
+              (Sec. 4), and the FSR-literature variants the GPU also offers:
+              non-zero concealed weighting, conjugate pairs, frequency prior,
+              residual-energy early stop.
   frame       Fig. 1 order (ME -> check -> projection -> FSR) for one frame,
               the causal recursion over a sequence, PSNR (Sec. 4).
   quality     mean SSIM reported beside PSNR (Sec. 4).
