@@ -429,7 +429,15 @@ class Sequence:
     reference, the projection and FSR (rfsr_frame_finish) wait for frame
     t-1.  Two workspaces alternate between frames.  The inputs of push()
     must be complete on the device when push() is called (pass `ready`, a
-    torch event, if they are still being produced)."""
+    torch event, if they are still being produced).
+
+    The ring holds the pushed tensors themselves (no copies): the measured
+    frame, the mask and the uint8 reconstruction of the last `nref` frames
+    are the next frames' references.  Their contents must not change while
+    they are (passing one unchanged tensor for every frame, e.g. a fixed
+    mask, is fine), and an out_u8 that is one of them raises RfsrError: the
+    call would overwrite a reference it reads (pass a fresh tensor, or
+    out_u8=None to allocate)."""
 
     def __init__(self, H, W, me: MEParams | None = None, fsr: FSRParams | None = None,
                  nref=3, device=None, pipelined=False):
@@ -459,6 +467,9 @@ class Sequence:
             self._fsr_start = None
 
     def push(self, meas, mask, stage_events=None, stream=None, out=None, out_u8=None, ready=None):
+        if out_u8 is not None and any(out_u8.data_ptr() == t.data_ptr() for r in self.ring for t in r):
+            raise RfsrError("Sequence.push: out_u8 is a plane the ring still holds as a reference; "
+                            "pass a fresh tensor or out_u8=None")
         refs = [(r[0], r[1], r[2]) for r in reversed(self.ring[-self.nref:])] if self.nref else []
         if not self.pipelined:
             out, out_u8 = reconstruct_frame(meas, mask, refs, self.me, self.fsr, out=out, out_u8=out_u8,

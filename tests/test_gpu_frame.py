@@ -80,6 +80,27 @@ def test_sequence_free_running_psnr():
         assert abs(p_g - p_o) <= PSNR_TOL
 
 
+def test_sequence_rejects_an_output_it_still_reads():
+    """An out_u8 that is one of the ring's reference planes would be
+    overwritten while the frame reads it: push() refuses it, in both modes;
+    one unchanged mask tensor for every frame is accepted."""
+    R = need_gpu()
+    rng = np.random.default_rng(22)
+    H = W = 32
+    frames, _ = synth.video_translate_edges(3, H, W, rng, max_step=1, n_edges=1)
+    mask = synth.fixed_mask(H, W, rng)
+    meas = synth.measured(frames, np.stack([mask] * 3))
+    m_d = dev(mask)
+    for pipelined in (False, True):
+        seq = R.Sequence(H, W, R.MEParams(search=3), R.FSRParams(iters=10), pipelined=pipelined)
+        u8 = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+        seq.push(dev(meas[0]), m_d, out_u8=u8)
+        with pytest.raises(R.RfsrError):
+            seq.push(dev(meas[1]), m_d, out_u8=u8)
+        seq.push(dev(meas[1]), m_d)
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("check", ["nnc_frmc", "rme", "rmc"])
 def test_frame_ignores_unmeasured_values(check):
     """Values of the current and the reference measured frames at unmeasured
