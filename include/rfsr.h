@@ -147,7 +147,8 @@ typedef struct {
  *            split as hi + lo in bfloat16, products hi*hi + hi*lo + lo*hi
  *            accumulated in float32.
  *   FP16X3   the same with float16 operands.
- *   FP32     every step in float32: FFT, table, residual and energies (the
+ *   FP32     every step in float32: FFT (w packed at 128 times its scale so
+ *            that W and w*s round alike), table, residual and energies (the
  *            plain float32 form).  Complex single bins and independent
  *            blocks only (pairs, concealed_weight > 0 and the literature
  *            options give RFSR_EUNSUPPORTED).

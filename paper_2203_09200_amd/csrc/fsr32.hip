@@ -3,8 +3,8 @@
 // measure what float64 costs and what it buys.  Same method (Sec. 2.1; Sec.
 // 3.2 for the projected samples and the overwrite; Sec. 4, concealed
 // weighting 0) and the same per-wavefront structure: one 64-lane wavefront
-// per 4x4 block, gather, 32x32 FFT of w*s + i*w, split into R = DFT(w*s) and
-// W = DFT(w), K greedy iterations, synthesis.
+// per 4x4 block, gather, 32x32 FFT of w*s + i*128*w, split into R = DFT(w*s)
+// and W = DFT(w) (times 128), K greedy iterations, synthesis.
 //
 // What float32 changes:
 //   * the W table is 8 KB (float2), so LDS admits four waves per SIMD instead
@@ -12,11 +12,14 @@
 //   * the argmax packs the support row into the 5 low mantissa bits of a
 //     float32 energy (ties broken at 2^-18 relative instead of 2^-47) and
 //     reduces one 32-bit word per lane;
-//   * W, computed in the same complex FFT as w*s, carries absolute errors at
-//     the scale of w*s, and the residual carries float32 rounding through
-//     every update, so late picks can depart from the float64 model: this
-//     form is not held to the 1e-3 output tolerance of the float64 one; its
-//     distance from the float64 model is measured instead.
+//   * W is computed in the same complex FFT as w*s; packed as w*s + i*w it
+//     would carry absolute errors at the scale of w*s (samples are 0..255),
+//     so the packed input is w*s + i*128*w and the scale cancels in
+//     gamma W / W(0);
+//   * the residual carries float32 rounding through every update, so late
+//     picks can still depart from the float64 model: this form is not held
+//     to the 1e-3 output tolerance of the float64 one; its distance from the
+//     float64 model is measured instead.
 //
 // Register layout of the iterations as in fsr.hip: lane (h, r) holds the bins
 // k = (j + 16 h, r), j = 0..15; W(k - b) for register j sits in table row
@@ -38,6 +41,11 @@ __device__ __forceinline__ uint32_t pack_energy32(float e, uint32_t code) {
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
 constexpr int kPlane32 = 33;   // padded row length of a transpose plane
+
+// The packed FFT carries w in its imaginary part scaled by 2^7, so that both
+// parts have the magnitude of w * s (samples are 0..255): float32 rounding
+// then errs on W relative to W, not to w * s.  A power of two scales exactly.
+constexpr float kWScale = 128.0f;
 
 }  // namespace
 
@@ -87,7 +95,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
             const float a = (k == 1u) ? 1.0f : projw;
             const float wv = known ? a * rw : 0.0f;
             zr[i] = wv * (known ? v : 0.0f);
-            zi[i] = wv;
+            zi[i] = wv * kWScale;
         }
     }
     __syncthreads();   // s_tw
@@ -140,8 +148,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         __syncthreads();
     }
     // The table holds g W with g = gamma / W0; the list keeps R_b.
-    const float W0 = __shfl(Wr[0], 0);
-    const float g = (W0 > 0.0f) ? gamma / W0 : 0.0f;
+    const float W0 = __shfl(Wr[0], 0);                   // kWScale * W(0)
+    const float g = (W0 > 0.0f) ? gamma / W0 : 0.0f;      // table: gamma * W / W(0), the scale cancels
     float2* T = reinterpret_cast<float2*>(smem);
 #pragma unroll
     for (int j = 0; j < 16; ++j) T[(j + 16 * h) * 32 + c] = make_float2(g * Wr[j], g * Wi[j]);
@@ -199,7 +207,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
     gr += __shfl_xor(gr, 16);
     gr += __shfl_xor(gr, 32);
-    gr *= g;
+    gr *= g * kWScale;   // dlt = gamma R_b / W(0)
     if (lane < 16) {
         const int y = 4 * bi + (p >> 2), x = 4 * bj + (p & 3);
         const int64_t off = (int64_t)y * pitch + x;

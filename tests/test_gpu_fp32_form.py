@@ -1,11 +1,12 @@
 """The plain float32 form of FSR (precision "fp32": FFT, table, residual and
 energies all float32) against the float64 oracle.  It is a comparison form,
-not held to the float64 kernel's 1e-3 bar: the tests pin that it computes
-the same method (the first picks, where energy gaps are large, agree with
-the oracle to float32 rounding of the data; over the full run the typical
-block stays far inside the 8-bit quantum and the frame PSNR within a few
-hundredths of a dB) and that it composes with the frame and batch paths
-bit for bit.  The measured distances are printed."""
+not held to the float64 kernel's 1e-3 bar in every block: float32 rounding
+of the residual can still change a late pick.  The tests pin that it
+computes the same method (the first picks agree with the oracle to float32
+rounding; over the full run at least 98 % of the unambiguous blocks stay
+within 1e-3 and the frame PSNR within 0.01 dB) and that it composes with
+the frame and batch paths bit for bit.  The measured distances are
+printed."""
 import numpy as np
 import pytest
 import torch
@@ -40,8 +41,8 @@ def test_fp32_form_first_picks_match_the_oracle(K):
     d = block_err(out, ora)
     amb = gaps < TAU_FP32
     print(f"K={K}: max {d[~amb].max():.2e}, median {np.median(d[~amb]):.2e}, ambiguous {amb.sum()}/{amb.size}")
-    assert d[~amb].max() <= 5e-3       # measured 1.4e-5 (K = 1), 3.2e-4 (K = 4)
-    assert np.median(d[~amb]) <= 5e-4
+    assert d[~amb].max() <= 1e-3
+    assert np.median(d[~amb]) <= 1e-4
     assert (host(u8) == np.rint(np.clip(out, 0, 255))).all()
 
 
@@ -57,11 +58,11 @@ def test_fp32_form_full_run_against_the_oracle():
     within = (d[~amb] <= 1e-3).mean()
     print(f"128x128 K=100 fp32: max {d.max():.3e}, median {np.median(d):.2e}, "
           f"unambiguous blocks within 1e-3: {within * 100:.1f} %, PSNR delta {dp:+.4f} dB")
-    # measured: median 1.2e-3, 43 % of the unambiguous blocks within 1e-3, PSNR +0.001 dB
+    # measured: median 4.5e-5, 99.8 % of the unambiguous blocks within 1e-3, PSNR -0.001 dB
     assert np.isfinite(out).all()
-    assert np.median(d[~amb]) < 0.02
-    assert within >= 0.25
-    assert abs(dp) <= 0.05
+    assert np.median(d[~amb]) < 1e-3
+    assert within >= 0.98
+    assert abs(dp) <= 0.01
 
 
 def test_fp32_form_1080p_sampled_blocks():
@@ -77,7 +78,8 @@ def test_fp32_form_1080p_sampled_blocks():
     amb = gaps < TAU_FP32
     print(f"1080p fp32 K=100: max {d[~amb].max():.2e}, median {np.median(d[~amb]):.2e}, "
           f"blocks > 1e-3: {(d[~amb] > 1e-3).mean() * 100:.1f} %")
-    assert np.median(d[~amb]) < 0.02   # measured 3.5e-4, 14 % of the blocks above 1e-3
+    assert np.median(d[~amb]) < 1e-3   # measured 2.8e-5, max 8.4e-5
+    assert (d[~amb] <= 1e-3).mean() >= 0.98
 
 
 def test_fp32_form_in_frame_path_and_batch():
@@ -129,7 +131,7 @@ def test_fp32_form_extreme_shapes(H, W):
     amb = gaps < TAU_FP32
     assert np.isfinite(out).all()
     if (~amb).any():
-        assert d[~amb].max() <= 5e-3
+        assert d[~amb].max() <= 1e-3
 
 
 def test_fp32_form_all_unknown_and_maximum_iterations():
@@ -146,4 +148,4 @@ def test_fp32_form_all_unknown_and_maximum_iterations():
     o64 = host(R.fsr_blocks(v_d, m_d, R.FSRParams(iters=1024))[0])
     assert np.isfinite(o32).all()
     print(f"K=1024: PSNR fp32 {O.psnr(f, o32, 8):.3f}, fp64 {O.psnr(f, o64, 8):.3f}")
-    assert abs(O.psnr(f, o32, 8) - O.psnr(f, o64, 8)) < 0.5
+    assert abs(O.psnr(f, o32, 8) - O.psnr(f, o64, 8)) < 0.1
