@@ -1,0 +1,74 @@
+"""Host logic of bench.py (CPU): the algorithmic flop count of an FSR block,
+percentiles, the PSNR report, the refusal of more than one GPU, and the
+gating of the committed counter record by the hash of the FSR kernel's
+sources."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2203_09200_amd import profiling  # noqa: E402
+
+
+def test_fsr_flops_per_block():
+    # 1024 complex bins x 11 flops per iteration, one 32x32 complex FFT
+    # (5 N log2 N), 16 pixels x 4 flops per synthesised coefficient
+    assert bench.fsr_flops_per_block(100) == 11 * 1024 * 100 + 5 * 1024 * 10 + 64 * 100 == 1_184_000
+    assert bench.fsr_flops_per_block(0) == 51_200
+    assert bench.fsr_flops_per_block(50, pairs=True) == 19 * 513 * 50 + 51_200 + 64 * 50
+
+
+def test_percentile():
+    xs = [5.0, 1.0, 3.0, 2.0, 4.0]
+    assert bench.percentile(xs, 50) == 3.0
+    assert bench.percentile(xs, 0) == 1.0 and bench.percentile(xs, 100) == 5.0
+    assert bench.percentile([1.0, 2.0], 50) == 1.5
+    assert bench.percentile([], 50) is None
+
+
+def test_psnr_report():
+    rng = np.random.default_rng(0)
+    ref = rng.integers(0, 256, (100, 120)).astype(np.uint8)
+    assert bench.psnr(ref, ref.astype(np.float32), border=10) == float("inf")
+    test = ref.astype(np.float64) + 2.0          # MSE 4 away from the clamp at 255
+    test[ref > 250] -= 4.0
+    mse = np.mean((ref[10:-10, 10:-10] - np.clip(test, 0, 255)[10:-10, 10:-10]) ** 2)
+    assert bench.psnr(ref, test, border=10) == pytest.approx(10 * np.log10(255.0 ** 2 / mse))
+
+
+def test_more_than_one_gpu_is_refused(capsys):
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU" in capsys.readouterr().err
+
+
+def test_counter_record_is_used_only_for_the_measured_sources(tmp_path, monkeypatch):
+    rec = {"kernel": "fsr_block_kernel", "bytes_per_launch": 123.0, "valu_insts_per_dispatch": 4.0}
+    (tmp_path / "profiles").mkdir()
+    path = tmp_path / "profiles" / "fsr_block_kernel_1080p_traffic.json"
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counters_from_profile() == {}                     # no record
+    path.write_text(json.dumps({**rec, "kernel_sha256": "0" * 64}))
+    assert bench.counters_from_profile() == {}                     # other sources
+    path.write_text(json.dumps({**rec, "kernel_sha256": profiling.kernel_digest()}))
+    assert bench.counters_from_profile()["bytes_per_launch"] == 123.0
+
+
+def test_kernel_digest_covers_every_source(tmp_path, monkeypatch):
+    csrc = tmp_path / "csrc"
+    csrc.mkdir()
+    for name in profiling.KERNEL_SOURCES:
+        (csrc / name).write_text(name)
+    monkeypatch.setattr(profiling, "HERE", str(tmp_path))
+    d0 = profiling.kernel_digest()
+    for name in profiling.KERNEL_SOURCES:
+        (csrc / name).write_text(name + " changed")
+        assert profiling.kernel_digest() != d0, name
+        (csrc / name).write_text(name)
+    assert profiling.kernel_digest() == d0
