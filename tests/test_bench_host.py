@@ -72,3 +72,30 @@ def test_kernel_digest_covers_every_source(tmp_path, monkeypatch):
         assert profiling.kernel_digest() != d0, name
         (csrc / name).write_text(name)
     assert profiling.kernel_digest() == d0
+
+
+def test_traffic_record_scales_counters_by_the_copy(tmp_path, monkeypatch):
+    """record(): the FSR kernel's FETCH_SIZE / WRITE_SIZE per dispatch, each
+    scaled by what the same counter reads for a copy of known size."""
+    def csv_file(name, rows):
+        p = tmp_path / name
+        lines = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+        lines += [f'{d},"{k}",{c},{v}' for d, k, c, v in rows]
+        p.write_text("\n".join(lines) + "\n")
+        return str(p)
+    kern = "void rfsr::fsr_block_kernel<0, false, false, 0>(args)"
+    ff = csv_file("ff.csv", [(1, kern, "FETCH_SIZE", 600.0), (2, kern, "FETCH_SIZE", 800.0),
+                             (3, "other_kernel", "FETCH_SIZE", 5.0)])
+    fw = csv_file("fw.csv", [(1, kern, "WRITE_SIZE", 1000.0), (2, kern, "WRITE_SIZE", 1000.0)])
+    cf = csv_file("cf.csv", [(1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 512.0)])
+    cw = csv_file("cw.csv", [(1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0)])
+    sq = csv_file("sq.csv", [(1, kern, "SQ_INSTS_VALU", 10.0), (2, kern, "SQ_INSTS_VALU", 14.0)])
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(profiling, "ROOT", str(tmp_path))
+    profiling.record(ff, fw, cf, cw, 1, "copyBuffer", sq_csv=sq)
+    rec = json.loads((tmp_path / "profiles" / "fsr_block_kernel_1080p_traffic.json").read_text())
+    # 1 MiB copied: FETCH_SIZE unit = 2^20 / 512 bytes, WRITE_SIZE unit = 2^20 / 1024 bytes
+    assert rec["fetch_scale_bytes_per_unit"] == 2048.0 and rec["write_scale_bytes_per_unit"] == 1024.0
+    assert rec["bytes_per_launch"] == 700.0 * 2048.0 + 1000.0 * 1024.0
+    assert rec["valu_insts_per_dispatch"] == 12.0
+    assert rec["kernel_sha256"] == profiling.kernel_digest()
