@@ -3,7 +3,14 @@ import numpy as np
 import pytest
 import torch
 
-TAU_FP32 = 1e-5      # relative energy gap below which an FSR block is tie-ambiguous in FP32
+# Relative energy gap below which an FSR block is tie-ambiguous (the greedy
+# argmax then has several correct answers).  The float64 kernel and the
+# float64 oracle differ by rounding of about 1e-13 relative (the packed row
+# code resolves 2^-47), so for them a gap of 1e-10 already decides; the
+# float32 forms and the 16-bit split DFTs carry float32 rounding.
+TAU_FP64 = 1e-10
+TAU_FP32 = 1e-5
+AMB_MAX = 0.005      # share of blocks that may be tie-ambiguous under TAU_FP64
 FSR_TOL = 1e-3       # max-abs tolerance of FSR outputs on the 0..255 scale
 PSNR_TOL = 0.01      # dB
 
@@ -28,7 +35,7 @@ def host(t):
     return t.cpu().numpy()
 
 
-def compare_fsr(gpu_out, ora_out, gaps, B=4, tol=FSR_TOL, tau=TAU_FP32):
+def compare_fsr(gpu_out, ora_out, gaps, B=4, tol=FSR_TOL, tau=TAU_FP64):
     """Blockwise comparison under the near-tie rule: blocks whose oracle
     energy gap is below tau are excluded from the max-abs check (counted).
     Returns (max_abs over unambiguous blocks, n_ambiguous, n_blocks)."""

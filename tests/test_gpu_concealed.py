@@ -8,7 +8,7 @@ import torch
 
 import oracle as O
 import synth
-from _gpu import FSR_TOL, PSNR_TOL, TAU_FP32, dev, host, need_gpu
+from _gpu import FSR_TOL, PSNR_TOL, TAU_FP64, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +33,7 @@ def test_concealed_fsr_teacher_forced(H, W, delta, K, overwrite):
     out = host(out)
     ora, gaps = O.fsr_frame_concealed(vals, cls, delta, K=K, overwrite=overwrite, given=out)
     d = np.abs(out - ora).reshape(H // 4, 4, W // 4, 4).max(axis=(1, 3))
-    amb = gaps < TAU_FP32
+    amb = gaps < TAU_FP64
     print(f"{H}x{W} delta={delta} K={K}: max {d[~amb].max():.2e}, ambiguous {amb.sum()}/{amb.size}")
     assert d[~amb].max() <= FSR_TOL
     assert (host(u8) == O.quantize(out)).all()

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 import synth
-from _gpu import FSR_TOL, PSNR_TOL, TAU_FP32, compare_fsr, dev, host, need_gpu
+from _gpu import FSR_TOL, PSNR_TOL, AMB_MAX, TAU_FP64, compare_fsr, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -84,7 +84,7 @@ def test_1080p_recursive_frame_sampled():
     ora, gaps = O.fsr.fsr_blocks_out(values, cls, blocks, K=100)
     got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
     d = np.abs(got - ora).max(axis=(1, 2))
-    amb = gaps < TAU_FP32
+    amb = gaps < TAU_FP64
     print(f"1080p frame 3: FSR max {d[~amb].max():.2e} over {(~amb).sum()} blocks, "
           f"projected {(cls == 2).mean():.3f} of pixels")
     assert d[~amb].max() <= FSR_TOL

@@ -6,7 +6,7 @@ import torch
 
 import oracle as O
 import synth
-from _gpu import FSR_TOL, PSNR_TOL, compare_fsr, dev, host, need_gpu
+from _gpu import AMB_MAX, FSR_TOL, PSNR_TOL, compare_fsr, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite
     print(f"frame {H}x{W} {check} {kind} nref={nref}: max {worst:.2e}, ambiguous {namb}/{nb}, "
           f"projected {(ora['cls'] == 2).mean():.3f}")
     assert worst <= FSR_TOL
-    assert namb <= 0.05 * nb
+    assert namb <= AMB_MAX * nb
     assert abs(O.psnr(frames[t], out, 8) - O.psnr(frames[t], ora["out"], 8)) <= PSNR_TOL
     assert (out_u8 == O.quantize(out)).all()
     return ora

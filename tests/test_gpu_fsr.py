@@ -8,7 +8,7 @@ import torch
 
 import oracle as O
 import synth
-from _gpu import FSR_TOL, PSNR_TOL, compare_fsr, dev, host, need_gpu
+from _gpu import AMB_MAX, FSR_TOL, TAU_FP64, PSNR_TOL, compare_fsr, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +39,7 @@ def test_fsr_parity(H, W, kind, K):
     print(f"FSR {H}x{W} {kind} K={K}: max|gpu-oracle| {worst:.2e} over unambiguous blocks, "
           f"{namb}/{nb} tie-ambiguous")
     assert worst <= FSR_TOL
-    assert namb <= 0.05 * nb
+    assert namb <= AMB_MAX * nb
     sl = (slice(8, -8), slice(8, -8))
     assert abs(O.psnr(f[sl], out[sl], 0) - O.psnr(f[sl], ora[sl], 0)) <= PSNR_TOL
     assert (out_u8 == O.quantize(out)).all()
@@ -123,7 +123,7 @@ def test_fsr_full_hd_sampled_blocks():
     ora_b, gaps = O.fsr.fsr_blocks_out(vals, m[0], blocks, K=100)
     got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
     d = np.abs(got - ora_b).max(axis=(1, 2))
-    amb = gaps < 1e-5
+    amb = gaps < TAU_FP64
     print(f"1080p sample: max {d[~amb].max():.2e}, ambiguous {amb.sum()}/256")
     assert d[~amb].max() <= FSR_TOL
-    assert amb.sum() <= 0.05 * 256
+    assert amb.sum() <= AMB_MAX * 256

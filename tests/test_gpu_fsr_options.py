@@ -10,7 +10,7 @@ import torch
 
 import oracle as O
 import synth
-from _gpu import FSR_TOL, PSNR_TOL, TAU_FP32, compare_fsr, dev, host, need_gpu
+from _gpu import FSR_TOL, PSNR_TOL, AMB_MAX, TAU_FP64, compare_fsr, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,7 @@ def test_fsr_options_frame_parity(sigma, ratio):
     print(f"sigma={sigma} ratio={ratio}: max {worst:.2e}, ambiguous {namb}/{nb}, "
           f"PSNR {O.psnr(f, out, 8):.3f} (oracle {O.psnr(f, ora, 8):.3f})")
     assert worst <= FSR_TOL
-    assert namb <= 0.05 * nb
+    assert namb <= AMB_MAX * nb
     assert abs(O.psnr(f, out, 8) - O.psnr(f, ora, 8)) <= PSNR_TOL
     assert (host(u8) == O.quantize(out)).all()
 
@@ -68,7 +68,7 @@ def test_fsr_options_in_the_frame_path():
                                  R.MEParams(search=8), R.FSRParams(iters=80, prior_sigma=0.85, stop_ratio=1e-3))
     worst, namb, nb = compare_fsr(host(out), ora["out"], ora["gaps"])
     print(f"frame path with prior + stop: max {worst:.2e}, ambiguous {namb}/{nb}")
-    assert worst <= FSR_TOL and namb <= 0.05 * nb
+    assert worst <= FSR_TOL and namb <= AMB_MAX * nb
 
 
 def test_fsr_options_1080p_sampled_blocks():
@@ -83,7 +83,7 @@ def test_fsr_options_1080p_sampled_blocks():
     out = host(out)
     got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
     d = np.abs(got - ora).max(axis=(1, 2))
-    amb = gaps < TAU_FP32
+    amb = gaps < TAU_FP64
     print(f"1080p prior + stop: max {d[~amb].max():.2e} over {(~amb).sum()} blocks")
     assert d[~amb].max() <= FSR_TOL
 
