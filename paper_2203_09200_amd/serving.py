@@ -14,10 +14,13 @@ one of `max_inflight` device streams.  Requests that arrive while batches
 run are admitted as soon as a batch slot and memory free up; batches on
 different device streams share no stream and therefore overlap on the GPU.
 
-Memory admission: `open_stream` admits a stream only if its ring and the
-workspace of one of its frames fit the budget next to the rings already
-open; a batch takes memory (job tables and workspace) from the budget until
-it retires, so the sum never exceeds the budget.
+Memory admission: `open_stream` admits a stream only if (a) its ring fits
+next to everything held now (the open rings and the batches in flight) and
+(b) all rings together leave room for the largest one-frame batch of any
+open stream, the new one included, so that every stream can always run
+alone once the batches in flight retire (no stream is starved by rings
+opened after it).  A batch takes memory (job tables and workspace) from the
+budget until it retires, so the sum never exceeds the budget.
 
 Executors: `GpuExecutor` runs batches through the C ABI (or, with
 mode="frame", one frame at a time through rfsr_reconstruct_frame: the plain
@@ -109,13 +112,20 @@ class Server:
         self._next_sid = 0
 
     # ---------------------------------------------------------- streams --
+    def _one_frame_bytes(self, H: int, W: int) -> int:
+        return self.ex.batch_bytes([(H, W, self.nref)])
+
     def open_stream(self, H: int, W: int) -> int:
         ring = self.ex.ring_bytes(H, W)
-        one = self.ex.batch_bytes([(H, W, self.nref)])
         rings = sum(s.ring_bytes for s in self.streams.values())
-        if rings + ring + one > self.budget:
-            raise AdmissionError(f"stream {H}x{W} does not fit the memory budget "
-                                 f"({rings + ring + one} > {self.budget} bytes)")
+        largest = max([self._one_frame_bytes(H, W)] +
+                      [self._one_frame_bytes(s.H, s.W) for s in self.streams.values()])
+        if rings + ring + largest > self.budget:
+            raise AdmissionError(f"stream {H}x{W} does not fit the memory budget: rings "
+                                 f"{rings + ring} + largest one-frame batch {largest} > {self.budget} bytes")
+        if self.used + ring > self.budget:
+            raise AdmissionError(f"stream {H}x{W} does not fit next to the memory held now "
+                                 f"({self.used} + {ring} > {self.budget} bytes); retry after batches retire")
         sid = self._next_sid
         self._next_sid += 1
         self.ex.open(sid, H, W)
@@ -441,6 +451,8 @@ def run_trace(server: Server, trace, payload, sids, clock: str = "real", sim=Non
             k += 1
         done = server.step(time.perf_counter())
         finished += done
+        if not done and not server.inflight and k == n and len(finished) < n:
+            raise RuntimeError("scheduler stalled with work pending")
         if progress and time.perf_counter() - last_print > 10.0:
             last_print = time.perf_counter()
             progress(f"t={now:.1f}s: {len(finished)}/{n} done, {server.pending()} pending")

@@ -135,3 +135,68 @@ def test_summarize_percentiles():
     assert st["latency_ms"]["p50"] == pytest.approx(50.5)
     assert st["latency_ms"]["p99"] == pytest.approx(99.01)
     assert st["latency_ms"]["max"] == pytest.approx(100.0)
+
+
+def test_admission_keeps_room_for_the_largest_frame_of_any_stream():
+    """A large stream opened first must still be able to run once smaller
+    streams opened after it hold their rings.  Here the 64x64 stream's ring
+    and frame fit, and the 8x8 stream's ring and frame would fit next to the
+    64x64 ring, but both rings together leave less than the 64x64 frame
+    needs: the second open is refused (admitted, the 64x64 frame could never
+    launch)."""
+    sim = S.SimExecutor()
+    ring64, one64 = sim.ring_bytes(64, 64), sim.batch_bytes([(64, 64, 3)])
+    ring8, one8 = sim.ring_bytes(8, 8), sim.batch_bytes([(8, 8, 3)])
+    budget = ring64 + one64 + ring8 // 2
+    assert ring64 + ring8 + one8 <= budget < ring64 + ring8 + one64
+    srv = S.Server(sim, budget)
+    srv.open_stream(64, 64)
+    with pytest.raises(S.AdmissionError):
+        srv.open_stream(8, 8)
+    # with room for both rings and the large frame, both run to completion
+    budget = ring64 + ring8 + one64
+    tr = [(0.0, 1, 0), (0.0, 0, 0), (0.001, 1, 1), (0.001, 0, 1)]
+    srv, sim2, reqs = run([(64, 64), (8, 8)], tr, budget=budget)
+    assert all(r.done is not None for r in reqs)
+    assert srv.peak <= budget
+
+
+def test_open_stream_counts_batches_in_flight():
+    """Opening a stream while batches hold memory never takes `used` past
+    the budget: the ring must fit next to what is held now, and the stream
+    is admitted once the batch has retired."""
+    sim = S.SimExecutor()
+    sim.clock = lambda: 0.0
+    ring, one = sim.ring_bytes(288, 352), sim.batch_bytes([(288, 352, 3)])
+    budget = 3 * ring + 2 * one - 1000
+    srv = S.Server(sim, budget, max_inflight=1)
+    a, b = srv.open_stream(288, 352), srv.open_stream(288, 352)
+    srv.submit(S.Request(a, 0, 0.0))
+    srv.submit(S.Request(b, 0, 0.0))
+    srv.step(0.0)                           # one batch of both frames in flight
+    assert len(srv.inflight) == 1 and len(srv.inflight[0].requests) == 2
+    assert srv.used == 2 * ring + sim.batch_bytes([(288, 352, 0)] * 2)
+    with pytest.raises(S.AdmissionError):
+        srv.open_stream(288, 352)           # rings + largest frame fit, but not next to the batch
+    assert srv.used <= budget
+    sim.clock = lambda: 1.0
+    srv.step(1.0)                           # the batch retires
+    assert not srv.inflight
+    srv.open_stream(288, 352)
+    assert srv.used <= budget
+
+
+@pytest.mark.timeout(60)
+def test_real_clock_loop_reports_a_stall():
+    """If nothing is in flight, nothing can launch and no arrivals are left,
+    the real-clock loop raises instead of spinning."""
+    class Stuck(S.SimExecutor):
+        def batch_bytes(self, shapes):        # every batch larger than any budget
+            return 1 << 60
+
+    sim = Stuck()
+    sim.clock = lambda: 0.0
+    srv = S.Server(sim, 1 << 40)
+    srv.streams[0] = S._Stream(0, 8, 8, 0)   # a stream admitted by an earlier rule
+    with pytest.raises(RuntimeError, match="stalled"):
+        S.run_trace(srv, [(0.0, 0, 0)], lambda s, i: (None, None), [0], clock="real")
