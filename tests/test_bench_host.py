@@ -99,3 +99,34 @@ def test_traffic_record_scales_counters_by_the_copy(tmp_path, monkeypatch):
     assert rec["bytes_per_launch"] == 700.0 * 2048.0 + 1000.0 * 1024.0
     assert rec["valu_insts_per_dispatch"] == 12.0
     assert rec["kernel_sha256"] == profiling.kernel_digest()
+
+
+def test_banded_oracle_equals_whole_frame_oracle():
+    """The CPU baseline's decomposition (motion path over row bands with
+    halos, projection, FSR over runs of block rows, as pool tasks) gives
+    exactly the whole-frame oracle's rows: at the bench's setting (R = 9,
+    NNC -> FRMC, the default halo) on a frame tall enough for crops whose
+    edges lie inside the frame, and for RME (the widest reach, 2R + 2 rows)
+    with a halo just above it."""
+    import multiprocessing as mp
+    import oracle as O
+    import synth
+    rng = np.random.default_rng(4)
+    fsr = O.FSRParams(iters=8)
+    with mp.get_context("spawn").Pool(2) as pool:
+        for H, W, R, check, y0, y1, band, halo in ((160, 40, 9, "nnc_frmc", 56, 104, 16, bench.ORACLE_HALO),
+                                                  (64, 32, 4, "rme", 8, 56, 8, 12)):
+            frames, _ = synth.video_translate_edges(4, H, W, rng, max_step=3, n_edges=3)
+            masks = synth.mask_sequence("dynamic", 4, H, W, rng)
+            meas = synth.measured(frames, masks)
+            recon = [np.clip(frames[t].astype(int) + rng.integers(-4, 5, (H, W)), 0, 255).astype(np.uint8)
+                     for t in range(3)]
+            refs = [(recon[2 - k], meas[2 - k], masks[2 - k]) for k in range(3)]
+            me = O.MEParams(search=R, check=check)
+            whole = O.reconstruct_frame(meas[3], masks[3], refs, me, fsr, track_gaps=False)["out"]
+            got = bench.oracle_frame_rows(pool, meas[3], masks[3], refs, me, fsr, y0, y1, band=band, halo=halo)
+            assert np.array_equal(got, whole[y0:y1]), (check, y0, y1)
+
+
+def test_cpu_cores_is_one_gpu_share():
+    assert 1 <= bench.cpu_cores() <= 16
