@@ -11,6 +11,7 @@
  *  - The library allocates no device memory.  Scratch space is the caller's
  *    `workspace` (device, >= rfsr_workspace_bytes(...) bytes, 256-byte
  *    aligned); its contents on entry are irrelevant and on exit undefined.
+ *    (fsr_blocks_noalloc uses a fixed array inside the library instead.)
  *  - All work is enqueued asynchronously on `stream` (a hipStream_t passed as
  *    void*; NULL is the default stream).  The return value reports argument
  *    validation and launch errors synchronously; a device fault of this call
@@ -213,6 +214,24 @@ rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32
                        int64_t pitch, const rfsr_fsr_params* fsr,
                        float* out, uint8_t* out_u8,
                        void* workspace, size_t ws_bytes, void* stream);
+
+/* fsr_blocks without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  The call allocates nothing; its scratch (the FSR
+ * tables, 17 KB) lives in an array inside the library of
+ * RFSR_NOALLOC_SCRATCH_BYTES per device, which every device that runs the
+ * library holds until the process ends.  All calls on one device share that
+ * device's array: calls that overlap on one device (different streams or
+ * threads) race, and the caller must serialise them.  The array keeps the
+ * last call's contents; nothing in it needs to start at zero (each call
+ * rewrites what it reads).  Arguments and results as fsr_blocks.
+ * Errors: as fsr_blocks; RFSR_EWORKSPACE if the request needs more scratch
+ * than the array holds; RFSR_EDEVICE if the array's device address cannot be
+ * obtained on the current device. */
+#define RFSR_NOALLOC_SCRATCH_BYTES 32768
+rfsr_status fsr_blocks_noalloc(const float* values, const uint8_t* cls, int32_t H, int32_t W,
+                               int64_t pitch, const rfsr_fsr_params* fsr,
+                               float* out, uint8_t* out_u8, void* stream);
 
 /* One recursive D-FSR / R-FSR frame in the order of Fig. 1: for each of the
  * nref (0..3) references, forward ME against its reconstruction and the

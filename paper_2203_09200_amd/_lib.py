@@ -104,6 +104,9 @@ def lib():
     L.rfsr_motion_check.restype = _STATUS
     L.rfsr_motion_check.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                     ctypes.POINTER(_MEParams), _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    L.fsr_blocks_noalloc.restype = _STATUS
+    L.fsr_blocks_noalloc.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                     ctypes.POINTER(_FSRParams), _P, _P, _P]
     L.fsr_blocks.restype = _STATUS
     L.fsr_blocks.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                              ctypes.POINTER(_FSRParams), _P, _P, _P, ctypes.c_size_t, _P]
@@ -277,6 +280,32 @@ def fsr_blocks(values, cls, fsr: FSRParams | None = None, want_u8=True,
     st = lib().fsr_blocks(_ptr(values), _ptr(cls), H, W, pitch, ctypes.byref(fc), _ptr(out),
                           _ptr(out_u8), _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "fsr_blocks")
+    return out, out_u8
+
+
+def fsr_blocks_noalloc(values, cls, fsr: FSRParams | None = None, out=None, out_u8=None, stream=None):
+    """fsr_blocks through the entry point that allocates nothing: its scratch
+    is the library's own device array.  `out` (float32) and `out_u8` (uint8,
+    optional) may be given with the pitch of `values`; missing `out` is
+    allocated here by torch, before the call.  Returns (out, out_u8)."""
+    fsr = fsr or FSRParams()
+    _plane(values, torch.float32, "values")
+    H, W = values.shape
+    _plane(cls, torch.uint8, "cls", (H, W))
+    pitch = values.stride(0)
+    if cls.stride(0) != pitch:
+        raise RfsrError("fsr_blocks_noalloc: values and cls must share the row pitch")
+    if out is None:
+        out = torch.empty_strided((H, W), (pitch, 1), dtype=torch.float32, device=values.device)
+    for t, dt, nm in ((out, torch.float32, "out"), (out_u8, torch.uint8, "out_u8")):
+        if t is not None:
+            _plane(t, dt, nm, (H, W))
+            if t.stride(0) != pitch:
+                raise RfsrError(f"fsr_blocks_noalloc: {nm} must have the pitch of values")
+    fc = fsr.c()
+    st = lib().fsr_blocks_noalloc(_ptr(values), _ptr(cls), H, W, pitch, ctypes.byref(fc), _ptr(out),
+                                  _ptr(out_u8), _stream(stream))
+    _check(st, "fsr_blocks_noalloc")
     return out, out_u8
 
 

@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -14,7 +15,7 @@ using namespace rfsr;
 
 namespace {
 
-constexpr int32_t kVersion = 10700;   // 1.7.0
+constexpr int32_t kVersion = 10800;   // 1.8.0
 constexpr int kMaxBatch = 4096;
 
 rfsr_status from_hip(hipError_t e) { return e == hipSuccess ? RFSR_OK : RFSR_EDEVICE; }
@@ -459,6 +460,68 @@ rfsr_status frame_call(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref
                               ws, L, static_cast<hipStream_t>(stream), part));
 }
 
+// --------------------------------------------------------- static scratch --
+// The scratch of fsr_blocks_noalloc: a file-scope device array, one copy per
+// device (each GPU that runs the library holds its own until the process
+// ends).  In host code `scratch` names a host-side stand-in, never the device
+// memory: its device address is looked up once per device with that device
+// current and kept in g_scratch; only that address is passed to kernels.
+constexpr size_t kStaticScratch = RFSR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kStaticScratch];
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device.
+rfsr_status static_scratch(void** p) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RFSR_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return RFSR_EDEVICE;
+        g_scratch[dev] = q;
+    }
+    *p = g_scratch[dev];
+    return RFSR_OK;
+}
+
+// Scratch bytes of one fsr_blocks call (the FSR tables).
+size_t fsr_blocks_scratch_bytes() { return align256(sizeof(FsrTables)); }
+
+rfsr_status check_blocks_args(const float* values, const uint8_t* cls, int32_t H, int32_t W, int64_t pitch,
+                              const rfsr_fsr_params* fsr, const float* out) {
+    if (!values || !cls || !out) return RFSR_EINVAL;
+    const rfsr_status st = check_shape(H, W, pitch);
+    if (st != RFSR_OK) return st;
+    return check_fsr(fsr);
+}
+
+// fsr_blocks on a validated request, its scratch (the FSR tables) at `workspace`.
+rfsr_status run_fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32_t W, int64_t pitch,
+                           const rfsr_fsr_params& fsr_p, float* out, uint8_t* out_u8, void* workspace,
+                           size_t ws_bytes, void* stream) {
+    const rfsr_fsr_params* fsr = &fsr_p;
+    rfsr_status st = check_ws(workspace, ws_bytes, fsr_blocks_scratch_bytes());
+    if (st != RFSR_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FsrTables* tab = static_cast<FsrTables*>(workspace);
+    FrameJob fj;
+    memset(&fj, 0, sizeof(fj));
+    fj.values = const_cast<float*>(values);   // read only by the FSR kernel
+    fj.cls = const_cast<uint8_t*>(cls);
+    fj.out = out;
+    fj.out_u8 = out_u8;
+    fj.pitch = pitch;
+    fj.opitch = pitch;
+    fj.vpitch = pitch;
+    fj.H = H;
+    fj.W = W;
+    hipError_t e = launch_fsr_tables(tab, fsr->rho, fsr->prior_sigma, s);
+    if (e == hipSuccess) e = launch_fsr(single(fj), (H / kBlock) * (W / kBlock), *fsr, tab, s);
+    return from_hip(e);
+}
+
 }  // namespace
 
 extern "C" {
@@ -515,27 +578,19 @@ rfsr_status rfsr_motion_check(const uint8_t* cur, const uint8_t* cur_mask, const
 rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32_t W, int64_t pitch,
                        const rfsr_fsr_params* fsr, float* out, uint8_t* out_u8, void* workspace,
                        size_t ws_bytes, void* stream) {
-    if (!values || !cls || !out) return RFSR_EINVAL;
-    rfsr_status st = check_shape(H, W, pitch);
+    const rfsr_status st = check_blocks_args(values, cls, H, W, pitch, fsr, out);
     if (st != RFSR_OK) return st;
-    if ((st = check_fsr(fsr)) != RFSR_OK) return st;
-    if ((st = check_ws(workspace, ws_bytes, align256(sizeof(FsrTables)))) != RFSR_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    FsrTables* tab = static_cast<FsrTables*>(workspace);
-    FrameJob fj;
-    memset(&fj, 0, sizeof(fj));
-    fj.values = const_cast<float*>(values);   // read only by the FSR kernel
-    fj.cls = const_cast<uint8_t*>(cls);
-    fj.out = out;
-    fj.out_u8 = out_u8;
-    fj.pitch = pitch;
-    fj.opitch = pitch;
-    fj.vpitch = pitch;
-    fj.H = H;
-    fj.W = W;
-    hipError_t e = launch_fsr_tables(tab, fsr->rho, fsr->prior_sigma, s);
-    if (e == hipSuccess) e = launch_fsr(single(fj), (H / kBlock) * (W / kBlock), *fsr, tab, s);
-    return from_hip(e);
+    return run_fsr_blocks(values, cls, H, W, pitch, *fsr, out, out_u8, workspace, ws_bytes, stream);
+}
+
+rfsr_status fsr_blocks_noalloc(const float* values, const uint8_t* cls, int32_t H, int32_t W, int64_t pitch,
+                               const rfsr_fsr_params* fsr, float* out, uint8_t* out_u8, void* stream) {
+    rfsr_status st = check_blocks_args(values, cls, H, W, pitch, fsr, out);
+    if (st != RFSR_OK) return st;
+    if (fsr_blocks_scratch_bytes() > kStaticScratch) return RFSR_EWORKSPACE;
+    void* ws = nullptr;
+    if ((st = static_scratch(&ws)) != RFSR_OK) return st;
+    return run_fsr_blocks(values, cls, H, W, pitch, *fsr, out, out_u8, ws, kStaticScratch, stream);
 }
 
 rfsr_status rfsr_reconstruct_frame(const uint8_t* cur, const uint8_t* cur_mask, int32_t nref,

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(R):
     lib = R.lib()
     for n in declared_functions():
         assert hasattr(lib, n), n
-    assert lib.rfsr_version() == 10700
+    assert lib.rfsr_version() == 10800
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.rfsr_status_string(code).startswith(b"RFSR_")
 
@@ -103,6 +103,24 @@ def test_fsr_blocks_rejects_bad_arguments(R):
     c = R.FSRParams().c()
     assert lib.fsr_blocks(None, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == -1
     assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 8, None) == -3
+
+
+def test_fsr_blocks_noalloc_rejects_bad_arguments(R):
+    """Argument validation of the entry point that allocates nothing runs
+    before it touches the device (its scratch array is looked up only for a
+    valid request)."""
+    lib = R.lib()
+    fake = ctypes.c_void_p(4096)
+    for kw, code in (({"iters": -1}, -1), ({"rho": 0.0}, -1), ({"gamma": 2.0}, -1), ({"block": 8}, -5),
+                     ({"precision": "fp32", "pairs": True}, -5)):
+        c = R.FSRParams(**kw).c()
+        assert lib.fsr_blocks_noalloc(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, None) == code, kw
+    c = R.FSRParams().c()
+    assert lib.fsr_blocks_noalloc(None, fake, 8, 8, 8, ctypes.byref(c), fake, None, None) == -1
+    assert lib.fsr_blocks_noalloc(fake, fake, 8, 8, 8, ctypes.byref(c), None, None, None) == -1
+    assert lib.fsr_blocks_noalloc(fake, fake, 8, 8, 8, None, fake, None, None) == -1
+    for H, W, pitch in ((6, 8, 8), (8, 10, 10), (8, 8, 4), (20000, 8, 8)):
+        assert lib.fsr_blocks_noalloc(fake, fake, H, W, pitch, ctypes.byref(c), fake, None, None) == -2
 
 
 def test_reconstruct_frame_rejects_bad_arguments(R):
