@@ -53,7 +53,7 @@ typedef enum {
  *             candidates [-rmc_radius, rmc_radius]^2 placed symmetrically
  *             around it (Sec. 3.1.1, Fig. 2b).
  *   FRMC      the same test with offsets {-7,-3,-1,0,1,3,7}^2 (Sec. 3.1.1,
- *             Fig. 2c).
+ *             Fig. 2c), or the set in rfsr_me_params.frmc.
  *   NNC       nearest-neighbour check on the 3x3 median filtered field
  *             (Sec. 3.1.2, Eq. (1), Fig. 2d).
  *   NNC_FRMC  NNC, then FRMC only where NNC accepted (Sec. 3.1.2, Table 3). */
@@ -74,13 +74,32 @@ typedef enum { RFSR_DFSR = 0, RFSR_RFSR = 1 } rfsr_overwrite;
  * Cost of vector v at pixel p, template offsets D = {-1,0,1,2}^2:
  *   S(p,v) = sum_{d in D, p+d in frame} b_t(p+d) |f_t(p+d) - Rhat(clamp(p+d+v))|
  * minimised over v in [-search, search]^2 with p+v in the frame, with the
- * total order (S, |v|_1, raster index of v).  Reverse costs are compared
- * normalised by the number of measured template pixels. */
+ * total order (S, |v|_1, raster index of v).  Reverse costs (RME, RMC, FRMC)
+ * belong to different current-frame pixels and are compared normalised by
+ * n, the number of measured template pixels (S_a n_b against S_b n_a).
+ *
+ * Options beside the paper's setting (defaults reproduce it):
+ *   n_frmc, frmc  FRMC's per-axis offset set (Sec. 3.1.1 prints
+ *                 {-7,-3,-1,0,1,3,7}; the Fig. 2 caption shows a small range
+ *                 {-2,-1,0,1,2}): n_frmc = 0 selects the paper's set, else
+ *                 frmc[0..n_frmc-1] (n_frmc <= 15) strictly increasing,
+ *                 containing 0, each |d| <= 14.  Used by FRMC and NNC_FRMC.
+ *   cost_norm     1: reverse costs compared as S/n (the default reading);
+ *                 0: raw S (an ablation of the normalisation).
+ *   nnc_center    RFSR_NNC_FILTERED: NNC compares the filtered vector at p
+ *                 with the filtered vectors of its four neighbours (the
+ *                 reading of Sec. 3.1.2); RFSR_NNC_RAW: the raw vector at p
+ *                 with the filtered neighbours. */
+typedef enum { RFSR_NNC_FILTERED = 0, RFSR_NNC_RAW = 1 } rfsr_nnc_center;
 typedef struct {
     int32_t tmpl;        /* template size; the library supports 4           */
     int32_t search;      /* search radius R, 0..15                            */
     int32_t check;       /* rfsr_check                                        */
     int32_t rmc_radius;  /* RMC radius, 0..15; 0 selects `search`             */
+    int32_t n_frmc;      /* 0..15 FRMC offsets in frmc[]; 0: the paper's set  */
+    int8_t frmc[16];     /* FRMC per-axis offsets (first n_frmc entries used) */
+    int32_t cost_norm;   /* 1: S/n (default); 0: raw S                        */
+    int32_t nnc_center;  /* rfsr_nnc_center                                   */
 } rfsr_me_params;
 
 /* Block-wise FSR (Sec. 2.1) with concealed weighting 0 (Sec. 4), so blocks
@@ -89,10 +108,13 @@ typedef struct {
  * pick the bin with the largest weighted residual energy, add
  * gamma * R_b / W0 to its coefficient, subtract it from the residual.
  * Weights: a * rho^(distance to the support centre), a = 1 measured,
- * proj_weight projected, 0 unknown / outside the frame.  The transform, the
- * residual spectrum and its energies are kept in float64 (full-rate on the
- * CDNA4 vector ALU); float32 drifts past the 1e-3 output tolerance within
- * 100 iterations. */
+ * proj_weight projected, 0 unknown / outside the frame.  By default the
+ * transform, the residual spectrum and its energies are float64 (`precision`
+ * below selects the other forms); the list of picks keeps R_b in float32
+ * and the output is float32, which bounds the output error near 1e-5 on the
+ * 0..255 scale.  In float32 the residual carries rounding of the order of
+ * 2^-24 times the block's spectral norm, which turns late near-tie picks the
+ * other way in about two blocks per thousand at K = 100. */
 typedef struct {
     int32_t block;       /* B; the library supports 4                        */
     int32_t support;     /* M; the library supports 32                       */

@@ -25,6 +25,9 @@ class MEParams:
     search: int = 9
     check: str = "nnc_frmc"
     rmc_radius: int | None = None
+    frmc: tuple | None = None         # per-axis FRMC offsets (None: {-7,-3,-1,0,1,3,7})
+    cost_norm: bool = True            # reverse costs compared as S/n (False: raw S)
+    nnc_center: str = "filtered"      # NNC compares the filtered ("filtered") or raw ("raw") vector at p
 
 
 @dataclass
@@ -60,7 +63,7 @@ def motion_fields(cur, cur_mask, refs, me: MEParams):
     for recon, meas, mask in refs:
         a, b, S, n = forward_me(cur, cur_mask, recon, me.search, me.tmpl)
         acc, ev = motion_check(me.check, cur, cur_mask, recon, a, b, me.search, me.tmpl,
-                               me.rmc_radius)
+                               me.rmc_radius, me.frmc, me.cost_norm, me.nnc_center)
         fields.append(dict(alpha=a, beta=b, S=S, n=n, accept=acc, evals=ev,
                            meas=meas, mask=mask))
     return fields

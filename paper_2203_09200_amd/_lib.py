@@ -29,7 +29,9 @@ class RfsrError(RuntimeError):
 
 class _MEParams(ctypes.Structure):
     _fields_ = [("tmpl", ctypes.c_int32), ("search", ctypes.c_int32),
-                ("check", ctypes.c_int32), ("rmc_radius", ctypes.c_int32)]
+                ("check", ctypes.c_int32), ("rmc_radius", ctypes.c_int32),
+                ("n_frmc", ctypes.c_int32), ("frmc", ctypes.c_int8 * 16),
+                ("cost_norm", ctypes.c_int32), ("nnc_center", ctypes.c_int32)]
 
 
 class _FSRParams(ctypes.Structure):
@@ -41,16 +43,30 @@ class _FSRParams(ctypes.Structure):
                 ("prior_sigma", ctypes.c_double), ("stop_ratio", ctypes.c_double)]
 
 
+NNC_CENTER = {"filtered": 0, "raw": 1}
+
+
 @dataclass
 class MEParams:
-    """Motion estimation and consistency check (Sec. 2.2, Sec. 3.1)."""
+    """Motion estimation and consistency check (Sec. 2.2, Sec. 3.1).
+    frmc: FRMC per-axis offsets (None: the paper's {-7,-3,-1,0,1,3,7});
+    cost_norm: compare reverse costs as S/n (False: raw S); nnc_center:
+    "filtered" or "raw" vector at p in NNC."""
     search: int = 9
     check: str = "nnc_frmc"
     rmc_radius: int = 0
     tmpl: int = 4
+    frmc: tuple | None = None
+    cost_norm: bool = True
+    nnc_center: str = "filtered"
 
     def c(self) -> _MEParams:
-        return _MEParams(self.tmpl, self.search, CHECKS[self.check], self.rmc_radius)
+        offs = () if self.frmc is None else tuple(int(d) for d in self.frmc)
+        if len(offs) > 16:
+            raise RfsrError("frmc: at most 15 offsets")
+        arr = (ctypes.c_int8 * 16)(*offs)
+        return _MEParams(self.tmpl, self.search, CHECKS[self.check], self.rmc_radius, len(offs), arr,
+                         int(bool(self.cost_norm)), NNC_CENTER[self.nnc_center])
 
 
 @dataclass

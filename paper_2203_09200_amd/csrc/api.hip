@@ -33,6 +33,19 @@ rfsr_status check_me(const rfsr_me_params* me) {
     if (me->search < 0 || me->search > kMaxSearch) return RFSR_EINVAL;
     if (me->check < RFSR_CHECK_NONE || me->check > RFSR_CHECK_NNC_FRMC) return RFSR_EINVAL;
     if (me->rmc_radius < 0 || me->rmc_radius > kMaxSearch) return RFSR_EINVAL;
+    if (me->cost_norm != 0 && me->cost_norm != 1) return RFSR_EINVAL;
+    if (me->nnc_center != RFSR_NNC_FILTERED && me->nnc_center != RFSR_NNC_RAW) return RFSR_EINVAL;
+    if (me->n_frmc < 0 || me->n_frmc > kMaxFrmc) return RFSR_EINVAL;
+    if (me->n_frmc > 0) {   // strictly increasing, containing 0, inside the window plane's reach
+        bool zero = false;
+        for (int i = 0; i < me->n_frmc; ++i) {
+            const int d = me->frmc[i];
+            if (d < -kMaxFrmcOffset || d > kMaxFrmcOffset) return RFSR_EINVAL;
+            if (i > 0 && d <= me->frmc[i - 1]) return RFSR_EINVAL;
+            zero |= d == 0;
+        }
+        if (!zero) return RFSR_EINVAL;
+    }
     if (me->tmpl != 4) return RFSR_EUNSUPPORTED;
     return RFSR_OK;
 }

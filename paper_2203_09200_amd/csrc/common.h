@@ -198,6 +198,17 @@ __host__ __device__ inline void wave_rows(int H, int W, int t, int& lo, int& hi)
 __host__ __device__ inline int wave_steps(int H, int W) { return 5 * (H / 4 - 1) + W / 4; }
 
 constexpr int kPad = 16;         // border of the window planes
+constexpr int kMaxFrmc = 15;     // FRMC offsets per axis in rfsr_me_params
+constexpr int kMaxFrmcOffset = kPad - 2;   // a template row at a red offset stays inside the window plane
+
+// Options of the consistency checks (from rfsr_me_params), by value to the
+// kernels: raw costs, the NNC centre and an FRMC offset set of the caller's.
+struct CheckOpts {
+    int raw;         // compare raw S instead of S/n
+    int nnc_raw;     // NNC compares the raw vector at p with the filtered neighbours
+    int nf;          // FRMC offsets per axis in f[] (0: the paper's set)
+    int8_t f[16];
+};
 constexpr int kMeTile = 16;      // forward ME tile edge
 constexpr int kFrmcRun = 2048;   // pixels per FRMC workgroup (cascade)
 

@@ -8,6 +8,8 @@
 // Forward ME takes the minimum of the key (S << 16 | |v|_1 << 10 | raster(v)),
 // a total order equal to (S, |v|_1, raster index of v) for R <= 15.
 // Reverse costs are compared as S/n by exact cross-multiplication.
+#include <string.h>
+
 #include "common.h"
 
 namespace rfsr {
@@ -316,7 +318,7 @@ __device__ __forceinline__ void ref_template(const RefJob& j, int qy, int qx, ui
 
 // Reverse motion field for RME: for every q the minimiser of
 // (S_rev/n_rev, |u|_1, raster(u)) over u in [-R,R]^2 with q+u in the frame.
-__global__ __launch_bounds__(256) void reverse_me_kernel(Jobs<RefJob> js, int R,
+__global__ __launch_bounds__(256) void reverse_me_kernel(Jobs<RefJob> js, int R, int raw,
                                                          unsigned long long* __restrict__ counters) {
     const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_px);
     if (j.H == 0) return;   // empty job (stale batch table)
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(256) void reverse_me_kernel(Jobs<RefJob> js, int R,
                 const int sx = qx + ux;
                 if ((unsigned)sx >= (unsigned)j.W) continue;
                 const uint32_t S = rev_cost(j, r, sy, sx);
-                const uint32_t n = j.nmap[(int64_t)sy * j.W + sx];
+                const uint32_t n = raw ? 1u : j.nmap[(int64_t)sy * j.W + sx];
                 const uint32_t l1 = (uint32_t)(abs(uy) + abs(ux));
                 const uint32_t lhs = S * bn, rhs = bS * n;
                 ++evals;
@@ -382,15 +384,15 @@ __device__ __forceinline__ bool projectable(const RefJob& j, int y, int x, int a
 }
 
 // RMC at pixel p with vector (a, b), offsets [-rr, rr]^2: accept iff
-// S(p,v)/n(p) < S(p+d, v-d)/n(p+d) for every red d with p+d in the frame.
-// Reds are tried in raster order and the test stops at the first loser.
-// evals counts the red costs evaluated.
-__device__ __forceinline__ bool rmc_test(const RefJob& j, int py, int px, int a, int b, int rr,
+// S(p,v)/n(p) < S(p+d, v-d)/n(p+d) (S(p,v) < S(p+d, v-d) with raw costs)
+// for every red d with p+d in the frame.  Reds are tried in raster order and
+// the test stops at the first loser.  evals counts the red costs evaluated.
+__device__ __forceinline__ bool rmc_test(const RefJob& j, int py, int px, int a, int b, int rr, int raw,
                                          unsigned long long& evals) {
     uint32_t r[4];
     ref_template(j, py + a, px + b, r);
     const uint32_t Sg = j.cost[(int64_t)py * j.cpitch + px];
-    const uint32_t ng = j.nmap[(int64_t)py * j.W + px];
+    const uint32_t ng = raw ? 1u : j.nmap[(int64_t)py * j.W + px];
     bool ok = true;
     for (int dy = -rr; dy <= rr && ok; ++dy) {
         const int sy = py + dy;
@@ -399,7 +401,7 @@ __device__ __forceinline__ bool rmc_test(const RefJob& j, int py, int px, int a,
             const int sx = px + dx;
             if ((dy | dx) == 0 || (unsigned)sx >= (unsigned)j.W) continue;
             const uint32_t S = rev_cost(j, r, sy, sx);
-            const uint32_t n = j.nmap[(int64_t)sy * j.W + sx];
+            const uint32_t n = raw ? 1u : j.nmap[(int64_t)sy * j.W + sx];
             ++evals;
             if (S * ng <= Sg * n) { ok = false; break; }
         }
@@ -407,54 +409,110 @@ __device__ __forceinline__ bool rmc_test(const RefJob& j, int py, int px, int a,
     return ok;
 }
 
-// FRMC at pixel p with vector (a, b), offsets {-7,-3,-1,0,1,3,7}^2: the
-// acceptance rule of rmc_test, organised for memory-level parallelism.  The
-// seven red candidates of one offset row are evaluated together: their 28
-// window reads have no branch between them (the padded window plane covers
-// offsets up to +-kPad, and an out-of-frame candidate only drops out of the
-// comparison).  The test stops after the first row that holds a loser;
-// evals counts the in-frame red costs of the rows evaluated.
-__device__ __forceinline__ bool frmc_test(const RefJob& j, int py, int px, int a, int b,
+// Red candidates of one FRMC offset row sy for a caller's offset set: true if
+// one of the candidates (sy, px + dxs[ix]) whose bit is set in `active` and
+// that lies in the frame is not worse than the green (reads up to +-kPad
+// columns stay inside the padded window plane; an out-of-frame candidate
+// only drops out of the comparison).  evals counts the in-frame reds.
+template <int N>
+__device__ __forceinline__ bool frmc_row_loses(const RefJob& j, const uint32_t (&r)[4], int sy, int px,
+                                               const int (&dxs)[N], uint32_t active, uint32_t Sg,
+                                               uint32_t ng, int raw, unsigned long long& evals) {
+    const int Wp = j.W + 2 * kPad;
+    const uint2* row = j.fm + (int64_t)(sy - 1 + kPad) * Wp + (px + kPad);
+    const uint8_t* nrow = j.nmap + (int64_t)sy * j.W;
+    bool lose = false;
+#pragma unroll
+    for (int ix = 0; ix < N; ++ix) {
+        if (!((active >> ix) & 1u)) continue;
+        const int dx = dxs[ix];
+        const int sx = px + dx;
+        const bool in = (unsigned)sx < (unsigned)j.W;
+        uint32_t S = 0;
+#pragma unroll
+        for (int dy = 0; dy < 4; ++dy) {
+            const uint2 v = row[dy * Wp + dx];
+            S = __builtin_amdgcn_sad_u8(v.x, r[dy] & v.y, S);
+        }
+        const uint32_t n = raw ? 1u : nrow[clampi(sx, 0, j.W - 1)];
+        evals += in;
+        lose |= in & (S * ng <= Sg * n);
+    }
+    return lose;
+}
+
+// FRMC at pixel p with vector (a, b): the acceptance rule of rmc_test over
+// the offsets {-7,-3,-1,0,1,3,7}^2, or with CUSTOM over the caller's set
+// o.f[0..o.nf-1]^2, organised for memory-level parallelism: the red
+// candidates of one offset row are evaluated together (for the paper's set
+// their 28 window reads have no branch between them: the padded window plane
+// covers offsets up to +-kPad, and an out-of-frame candidate only drops out
+// of the comparison), and the test stops after the first row that holds a
+// loser; evals counts the in-frame red costs of the rows evaluated.
+template <bool CUSTOM>
+__device__ __forceinline__ bool frmc_test(const RefJob& j, int py, int px, int a, int b, const CheckOpts& o,
                                           unsigned long long& evals) {
-    static_assert(kPad >= 7 + 2, "window plane border must cover the FRMC offsets and the template");
-    constexpr int kOff[7] = {-7, -3, -1, 0, 1, 3, 7};
+    static_assert(kPad >= 7 + 2 && kMaxFrmcOffset + 2 <= kPad,
+                  "window plane border must cover the FRMC offsets and the template");
     uint32_t r[4];
     ref_template(j, py + a, px + b, r);
     const uint32_t Sg = j.cost[(int64_t)py * j.cpitch + px];
-    const uint32_t ng = j.nmap[(int64_t)py * j.W + px];
-    const int Wp = j.W + 2 * kPad;
+    const uint32_t ng = o.raw ? 1u : j.nmap[(int64_t)py * j.W + px];
+    if constexpr (!CUSTOM) {
+        constexpr int kOff[7] = {-7, -3, -1, 0, 1, 3, 7};
+        const int Wp = j.W + 2 * kPad;
 #pragma unroll
-    for (int iy = 0; iy < 7; ++iy) {
-        const int sy = py + kOff[iy];
-        if ((unsigned)sy >= (unsigned)j.H) continue;
-        const uint2* row = j.fm + (int64_t)(sy - 1 + kPad) * Wp + (px + kPad);
-        const uint8_t* nrow = j.nmap + (int64_t)sy * j.W;
-        bool lose = false;
+        for (int iy = 0; iy < 7; ++iy) {
+            const int sy = py + kOff[iy];
+            if ((unsigned)sy >= (unsigned)j.H) continue;
+            const uint2* row = j.fm + (int64_t)(sy - 1 + kPad) * Wp + (px + kPad);
+            const uint8_t* nrow = j.nmap + (int64_t)sy * j.W;
+            bool lose = false;
 #pragma unroll
-        for (int ix = 0; ix < 7; ++ix) {
-            if (iy == 3 && ix == 3) continue;   // the green candidate
-            const int dx = kOff[ix];
-            const int sx = px + dx;
-            const bool in = (unsigned)sx < (unsigned)j.W;
-            uint32_t S = 0;
+            for (int ix = 0; ix < 7; ++ix) {
+                if (iy == 3 && ix == 3) continue;   // the green candidate
+                const int dx = kOff[ix];
+                const int sx = px + dx;
+                const bool in = (unsigned)sx < (unsigned)j.W;
+                uint32_t S = 0;
 #pragma unroll
-            for (int dy = 0; dy < 4; ++dy) {
-                const uint2 v = row[dy * Wp + dx];
-                S = __builtin_amdgcn_sad_u8(v.x, r[dy] & v.y, S);
+                for (int dy = 0; dy < 4; ++dy) {
+                    const uint2 v = row[dy * Wp + dx];
+                    S = __builtin_amdgcn_sad_u8(v.x, r[dy] & v.y, S);
+                }
+                const uint32_t n = o.raw ? 1u : nrow[clampi(sx, 0, j.W - 1)];
+                evals += in;
+                lose |= in & (S * ng <= Sg * n);   // no short circuit: the reads stay unconditional
             }
-            const uint32_t n = nrow[clampi(sx, 0, j.W - 1)];
-            evals += in;
-            lose |= in & (S * ng <= Sg * n);   // no short circuit: the reads stay unconditional
+            if (lose) return false;
         }
-        if (lose) return false;
+    } else {
+        // the caller's offsets, copied with constant indices (entries beyond
+        // o.nf are inactive and read column offset 0, inside the plane)
+        int off[kMaxFrmc];
+        uint32_t all = 0, green = 0;
+#pragma unroll
+        for (int i = 0; i < kMaxFrmc; ++i) {
+            off[i] = i < o.nf ? (int)o.f[i] : 0;
+            all |= (i < o.nf ? 1u : 0u) << i;
+            green |= (i < o.nf && o.f[i] == 0 ? 1u : 0u) << i;
+        }
+#pragma unroll
+        for (int iy = 0; iy < kMaxFrmc; ++iy) {
+            if (iy >= o.nf) break;
+            const int sy = py + off[iy];
+            if ((unsigned)sy >= (unsigned)j.H) continue;
+            const uint32_t active = off[iy] == 0 ? all & ~green : all;
+            if (frmc_row_loses(j, r, sy, px, off, active, Sg, ng, o.raw, evals)) return false;
+        }
     }
     return true;
 }
 
 // RMC / FRMC over every pixel (stand-alone checks); with a reference mask
 // only projectable pixels are tested and the decision elsewhere is 0.
-template <bool DENSE>
-__global__ __launch_bounds__(256) void rmc_kernel(Jobs<RefJob> js, int rr,
+template <bool DENSE, bool CUSTOM>
+__global__ __launch_bounds__(256) void rmc_kernel(Jobs<RefJob> js, int rr, CheckOpts opts,
                                                   unsigned long long* __restrict__ counters) {
     const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_px);
     if (j.H == 0) return;   // empty job (stale batch table)
@@ -467,7 +525,8 @@ __global__ __launch_bounds__(256) void rmc_kernel(Jobs<RefJob> js, int rr,
         bool ok = projectable(j, py, px, a, b);
         if (ok) {
             checked = 1;
-            ok = DENSE ? rmc_test(j, py, px, a, b, rr, evals) : frmc_test(j, py, px, a, b, evals);
+            ok = DENSE ? rmc_test(j, py, px, a, b, rr, opts.raw, evals)
+                       : frmc_test<CUSTOM>(j, py, px, a, b, opts, evals);
         }
         j.accept[o] = ok;
         accepted = ok;
@@ -489,7 +548,8 @@ __global__ __launch_bounds__(256) void rmc_kernel(Jobs<RefJob> js, int rr,
 // reference mask, projectable) into an LDS list, then runs FRMC over that
 // list with all its threads, so that waves stay full although most pixels
 // need no test.  Every pixel of the run gets its decision written.
-__global__ __launch_bounds__(256) void frmc_tile_kernel(Jobs<RefJob> js,
+template <bool CUSTOM>
+__global__ __launch_bounds__(256) void frmc_tile_kernel(Jobs<RefJob> js, CheckOpts opts,
                                                         unsigned long long* __restrict__ counters) {
     __shared__ int s_list[kFrmcRun];
     __shared__ unsigned s_n;
@@ -527,7 +587,7 @@ __global__ __launch_bounds__(256) void frmc_tile_kernel(Jobs<RefJob> js,
         const int e = s_list[i];
         const int py = e / j.W, px = e - py * j.W;
         const int64_t o = (int64_t)py * j.opitch + px;
-        const bool ok = frmc_test(j, py, px, j.mv_a[o], j.mv_b[o], evals);
+        const bool ok = frmc_test<CUSTOM>(j, py, px, j.mv_a[o], j.mv_b[o], opts, evals);
         j.accept[o] = ok;
         accepted += ok;
     }
@@ -587,8 +647,9 @@ __global__ void median_kernel(Jobs<RefJob> js) {
     j.mb[e] = (int8_t)median9(vb);
 }
 
-// NNC decision (the cascade's FRMC reads it back from `accept`).
-__global__ void nnc_kernel(Jobs<RefJob> js, unsigned long long* counters, bool count) {
+// NNC decision (the cascade's FRMC reads it back from `accept`).  With
+// center_raw the raw vector at p is compared with the filtered neighbours.
+__global__ void nnc_kernel(Jobs<RefJob> js, int center_raw, unsigned long long* counters, bool count) {
     const RefJob j = job_at(js, (int)blockIdx.x, &RefJob::g_px);
     if (j.H == 0) return;   // empty job (stale batch table)
     const int e = ((int)blockIdx.x - j.g_px) * 256 + (int)threadIdx.x;
@@ -598,13 +659,15 @@ __global__ void nnc_kernel(Jobs<RefJob> js, unsigned long long* counters, bool c
         const int y = e / W, x = e - y * W;
         const int8_t* __restrict__ ma = j.ma;
         const int8_t* __restrict__ mb = j.mb;
-        const int a = ma[e], b = mb[e];
+        const int64_t o = (int64_t)y * j.opitch + x;
+        const int a = center_raw ? (int)j.mv_a[o] : (int)ma[e];
+        const int b = center_raw ? (int)j.mv_b[o] : (int)mb[e];
         bool ok = true;
         if (y > 0) ok &= abs(a - ma[e - W]) + abs(b - mb[e - W]) <= 1;
         if (y < H - 1) ok &= abs(a - ma[e + W]) + abs(b - mb[e + W]) <= 1;
         if (x > 0) ok &= abs(a - ma[e - 1]) + abs(b - mb[e - 1]) <= 1;
         if (x < W - 1) ok &= abs(a - ma[e + 1]) + abs(b - mb[e + 1]) <= 1;
-        j.accept[(int64_t)y * j.opitch + x] = ok;
+        j.accept[o] = ok;
         acc_cnt = ok;
     }
     if (count && counters) {
@@ -703,31 +766,42 @@ hipError_t launch_motion(const Jobs<RefJob>& js, int total_tiles, int total_px, 
     hipError_t err = launch_me(me.search, js, total_tiles, counters, s);
     if (err != hipSuccess) return err;
     const int rr = me.rmc_radius > 0 ? me.rmc_radius : me.search;
+    CheckOpts opts;
+    memset(&opts, 0, sizeof(opts));
+    opts.raw = me.cost_norm == 0;
+    opts.nnc_raw = me.nnc_center == RFSR_NNC_RAW;
+    opts.nf = me.n_frmc;
+    for (int i = 0; i < me.n_frmc && i < kMaxFrmc; ++i) opts.f[i] = me.frmc[i];
+    const bool custom = opts.nf > 0;
     const dim3 gpx(total_px), blk(256);
     switch (me.check) {
         case RFSR_CHECK_NONE:
             hipLaunchKernelGGL(accept_all_kernel, gpx, blk, 0, s, js, counters);
             break;
         case RFSR_CHECK_RME:
-            hipLaunchKernelGGL(reverse_me_kernel, gpx, blk, 0, s, js, me.search, counters);
+            hipLaunchKernelGGL(reverse_me_kernel, gpx, blk, 0, s, js, me.search, opts.raw, counters);
             if ((err = hipGetLastError()) != hipSuccess) return err;
             hipLaunchKernelGGL(rme_accept_kernel, gpx, blk, 0, s, js, counters);
             break;
         case RFSR_CHECK_RMC:
-            hipLaunchKernelGGL((rmc_kernel<true>), gpx, blk, 0, s, js, rr, counters);
+            hipLaunchKernelGGL((rmc_kernel<true, false>), gpx, blk, 0, s, js, rr, opts, counters);
             break;
         case RFSR_CHECK_FRMC:
-            hipLaunchKernelGGL((rmc_kernel<false>), gpx, blk, 0, s, js, rr, counters);
+            if (custom) hipLaunchKernelGGL((rmc_kernel<false, true>), gpx, blk, 0, s, js, rr, opts, counters);
+            else hipLaunchKernelGGL((rmc_kernel<false, false>), gpx, blk, 0, s, js, rr, opts, counters);
             break;
         case RFSR_CHECK_NNC:
         case RFSR_CHECK_NNC_FRMC: {
             const bool cascade = me.check == RFSR_CHECK_NNC_FRMC;
             hipLaunchKernelGGL(median_kernel, gpx, blk, 0, s, js);
             if ((err = hipGetLastError()) != hipSuccess) return err;
-            hipLaunchKernelGGL(nnc_kernel, gpx, blk, 0, s, js, counters, !cascade);
+            hipLaunchKernelGGL(nnc_kernel, gpx, blk, 0, s, js, opts.nnc_raw, counters, !cascade);
             if (cascade) {
                 if ((err = hipGetLastError()) != hipSuccess) return err;
-                hipLaunchKernelGGL(frmc_tile_kernel, dim3(total_frmc), blk, 0, s, js, counters);
+                if (custom)
+                    hipLaunchKernelGGL(frmc_tile_kernel<true>, dim3(total_frmc), blk, 0, s, js, opts, counters);
+                else
+                    hipLaunchKernelGGL(frmc_tile_kernel<false>, dim3(total_frmc), blk, 0, s, js, opts, counters);
             }
             break;
         }

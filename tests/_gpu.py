@@ -44,3 +44,32 @@ def compare_fsr(gpu_out, ora_out, gaps, B=4, tol=FSR_TOL, tau=TAU_FP64):
     amb = gaps < tau
     worst = d[~amb].max() if (~amb).any() else 0.0
     return float(worst), int(amb.sum()), int(amb.size)
+
+
+def check_support_fields(cur, mask, recon, alpha, beta, accept, cost, blocks, search, pad=16):
+    """For each listed FSR block, recompute with the oracle on a crop around
+    its 32x32 support (plus `pad` rows and columns, more than the reach of
+    forward ME feeding the NNC medians and of FRMC, so the crop's own edges do
+    not matter inside the support) the forward vectors and costs on the
+    support grown by 2 pixels, and the NNC -> FRMC decisions on the support,
+    and assert that the GPU's full-frame planes equal them there.  Returns the
+    number of support pixels checked."""
+    import oracle as O
+    H, W = cur.shape
+    checked = 0
+    for bi, bj in blocks:
+        sy0, sx0 = max(0, 4 * bi - 14), max(0, 4 * bj - 14)
+        sy1, sx1 = min(H, 4 * bi + 18), min(W, 4 * bj + 18)
+        cy0, cx0 = max(0, sy0 - 2 - pad), max(0, sx0 - 2 - pad)
+        cy1, cx1 = min(H, sy1 + 2 + pad), min(W, sx1 + 2 + pad)
+        crop = (slice(cy0, cy1), slice(cx0, cx1))
+        a, b, S, _ = O.forward_me(cur[crop], mask[crop], recon[crop], search)
+        g = (slice(max(0, sy0 - 2) - cy0, min(H, sy1 + 2) - cy0), slice(max(0, sx0 - 2) - cx0, min(W, sx1 + 2) - cx0))
+        gf = (slice(max(0, sy0 - 2), min(H, sy1 + 2)), slice(max(0, sx0 - 2), min(W, sx1 + 2)))
+        assert np.array_equal(a[g], alpha[gf]) and np.array_equal(b[g], beta[gf]), (bi, bj)
+        assert np.array_equal(S[g], cost[gf]), (bi, bj)
+        acc, _ = O.motion_check("nnc_frmc", cur[crop], mask[crop], recon[crop], a, b, search)
+        sup = (slice(sy0 - cy0, sy1 - cy0), slice(sx0 - cx0, sx1 - cx0))
+        assert np.array_equal(acc[sup], accept[sy0:sy1, sx0:sx1]), (bi, bj)
+        checked += (sy1 - sy0) * (sx1 - sx0)
+    return checked

@@ -123,6 +123,38 @@ def test_fsr_blocks_noalloc_rejects_bad_arguments(R):
         assert lib.fsr_blocks_noalloc(fake, fake, H, W, pitch, ctypes.byref(c), fake, None, None) == -2
 
 
+def test_me_params_options_validation(R):
+    """The FRMC offset set, cost_norm and nnc_center are validated before any
+    device work (rfsr_workspace_bytes returns 0 for invalid parameters)."""
+    lib = R.lib()
+
+    def ws(**kw):
+        p = R.MEParams(**kw).c()
+        return lib.rfsr_workspace_bytes(64, 64, 1, ctypes.byref(p), None)
+
+    assert ws() > 0
+    assert ws(frmc=(-2, -1, 0, 1, 2)) > 0
+    assert ws(frmc=tuple(range(-14, 1))) > 0                 # 15 offsets, reach 14
+    assert ws(frmc=(0,)) > 0
+    assert ws(cost_norm=False, nnc_center="raw") > 0
+    for bad in ((-2, -1, 1, 2), (-1, 0, 0, 1), (1, 0, -1), (-15, 0), (0, 15), tuple(range(-15, 1))):
+        assert ws(frmc=bad) == 0, bad
+    p = R.MEParams().c()
+    p.cost_norm = 2
+    assert lib.rfsr_workspace_bytes(64, 64, 1, ctypes.byref(p), None) == 0
+    p = R.MEParams().c()
+    p.nnc_center = 2
+    assert lib.rfsr_workspace_bytes(64, 64, 1, ctypes.byref(p), None) == 0
+    p = R.MEParams().c()
+    p.n_frmc = 16
+    assert lib.rfsr_workspace_bytes(64, 64, 1, ctypes.byref(p), None) == 0
+    # the same validation guards the calls themselves
+    fake = ctypes.c_void_p(4096)
+    p = R.MEParams(frmc=(-2, 2)).c()
+    assert lib.rfsr_motion_check(fake, fake, fake, 8, 8, 8, ctypes.byref(p), fake, fake, None, None,
+                                 fake, 1 << 20, None) == -1
+
+
 def test_reconstruct_frame_rejects_bad_arguments(R):
     lib = R.lib()
     P = ctypes.c_void_p

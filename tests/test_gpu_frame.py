@@ -11,7 +11,7 @@ from _gpu import AMB_MAX, FSR_TOL, PSNR_TOL, compare_fsr, dev, host, need_gpu
 pytestmark = pytest.mark.gpu
 
 
-def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite="dfsr"):
+def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite="dfsr", me_opts=None):
     R = need_gpu()
     rng = np.random.default_rng(seed)
     frames, _ = synth.video_translate_edges(nref + 1, H, W, rng, max_step=3, n_edges=3)
@@ -22,12 +22,13 @@ def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite
     recon = [np.clip(frames[t - 1 - k].astype(int) + rng.integers(-3, 4, (H, W)), 0, 255).astype(np.uint8)
              for k in range(nref)]
     refs = [(recon[k], meas[t - 1 - k], masks[t - 1 - k]) for k in range(nref)]
-    me = O.MEParams(search=search, check=check)
+    me_opts = me_opts or {}
+    me = O.MEParams(search=search, check=check, **me_opts)
     fsr = O.FSRParams(iters=K, overwrite=overwrite)
     ora = O.reconstruct_frame(meas[t], masks[t], refs, me, fsr)
     out, out_u8 = R.reconstruct_frame(dev(meas[t]), dev(masks[t]),
                                       [(dev(r), dev(mm), dev(b)) for r, mm, b in refs],
-                                      R.MEParams(search=search, check=check),
+                                      R.MEParams(search=search, check=check, **me_opts),
                                       R.FSRParams(iters=K, overwrite=overwrite))
     out, out_u8 = host(out), host(out_u8)
     worst, namb, nb = compare_fsr(out, ora["out"], ora["gaps"])

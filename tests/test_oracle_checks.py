@@ -65,8 +65,9 @@ def test_reverse_cost_identity():
             assert (S1[ins] == S2[ins]).all() and (n1[ins] == n2[ins]).all()
 
 
-def brute_reverse(cur, mask, ref, R):
-    """Explicit loops, exact rational comparison via fractions."""
+def brute_reverse(cur, mask, ref, R, norm=True):
+    """Explicit loops, exact rational comparison via fractions (raw S
+    without `norm`)."""
     from fractions import Fraction
     H, W = cur.shape
     UA = np.zeros((H, W), int)
@@ -87,7 +88,7 @@ def brute_reverse(cur, mask, ref, R):
                                 t = ref[min(max(y + dy, 0), H - 1), min(max(x + dx, 0), W - 1)]
                                 s += abs(int(cur[cy, cx]) - int(t))
                                 n += 1
-                    key = (Fraction(s, n), abs(uy) + abs(ux))
+                    key = (Fraction(s, n) if norm else Fraction(s), abs(uy) + abs(ux))
                     if best is None or key < best[0]:
                         best = (key, uy, ux)
             UA[y, x], UB[y, x] = best[1], best[2]
@@ -105,7 +106,7 @@ def test_reverse_me_matches_brute_force():
     assert (ua == UA).all() and (ub == UB).all()
 
 
-def brute_rmc(cur, mask, ref, a, b, offsets):
+def brute_rmc(cur, mask, ref, a, b, offsets, norm=True):
     from fractions import Fraction
     H, W = cur.shape
 
@@ -118,7 +119,7 @@ def brute_rmc(cur, mask, ref, a, b, offsets):
                     r = ref[min(max(qy + vy, 0), H - 1), min(max(qx + vx, 0), W - 1)]
                     s += abs(int(cur[qy, qx]) - int(r))
                     n += 1
-        return Fraction(s, n)
+        return Fraction(s, n) if norm else Fraction(s)
 
     acc = np.zeros((H, W), bool)
     for y in range(H):
@@ -222,3 +223,104 @@ def test_rmc_accept_at_equals_full_frame():
         ys, xs = np.mgrid[0:H, 0:W]
         at = O.rmc_accept_at(cur, m, frames[0], ys.ravel(), xs.ravel(), a.ravel(), b.ravel(), offs)
         assert np.array_equal(at.reshape(H, W), full)
+
+
+# ---- options beside the readings: raw costs, raw NNC centre, FRMC offset sets
+
+def test_raw_cost_checks_match_brute_force():
+    """cost_norm=False compares raw S: RME and RMC/FRMC against explicit loops
+    with exact integer comparison, and the raw reading differs from the
+    normalised one on this quarter-sampled frame (n varies from 1 to 9)."""
+    rng = np.random.default_rng(6)
+    H, W = 12, 12
+    frames, _ = synth.video_translate_edges(2, H, W, rng, max_step=1)
+    mask = synth.fixed_mask(H, W, rng)
+    cur = synth.measured(frames[1], mask)
+    ref = np.clip(frames[0].astype(int) + rng.integers(-20, 21, (H, W)), 0, 255).astype(np.uint8)
+    ua, ub, _ = O.reverse_me(cur, mask, ref, 2, cost_norm=False)
+    UA, UB = brute_reverse(cur, mask, ref, 2, norm=False)
+    assert (ua == UA).all() and (ub == UB).all()
+    a, b, _, _ = O.forward_me(cur, mask, ref, 2)
+    differ = 0
+    for offs in (O.rmc_offsets(2), O.frmc_offsets(), np.array([-3, 0, 2])):
+        raw, _ = O.rmc_accept(cur, mask, ref, a, b, offs, cost_norm=False)
+        assert (raw == brute_rmc(cur, mask, ref, a, b, offs, norm=False)).all()
+        nrm, _ = O.rmc_accept(cur, mask, ref, a, b, offs)
+        differ += int((raw != nrm).sum())
+    assert differ > 0
+
+
+def test_raw_and_normalised_costs_agree_when_n_is_constant():
+    """With every pixel measured, n = 16 at every template inside the frame,
+    so comparing S or S/n decides alike for pixels whose candidates all lie
+    at least 2 pixels inside the frame."""
+    rng = np.random.default_rng(7)
+    H, W = 20, 20
+    cur = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    ref = np.clip(np.roll(cur, 1, axis=1).astype(int) + rng.integers(-30, 31, (H, W)), 0, 255).astype(np.uint8)
+    full = np.ones((H, W), np.uint8)
+    a, b, _, _ = O.forward_me(cur, full, ref, 2)
+    offs = O.rmc_offsets(2)
+    raw, _ = O.rmc_accept(cur, full, ref, a, b, offs, cost_norm=False)
+    nrm, _ = O.rmc_accept(cur, full, ref, a, b, offs)
+    inner = (slice(6, -6), slice(6, -6))
+    assert np.array_equal(raw[inner], nrm[inner])
+
+
+def test_nnc_raw_center_hand_worked():
+    g = read_grids("nnc_outlier.txt")
+    acc = O.nnc_accept(g["alpha"], g["beta"], center="raw")
+    assert (acc.astype(int) == g["accept_raw_center"]).all()
+    # the two readings differ exactly at the isolated outlier
+    lit = O.nnc_accept(g["alpha"], g["beta"])
+    assert list(zip(*np.nonzero(acc != lit))) == [(1, 2)]
+
+
+def test_nnc_raw_center_uniform_field():
+    a = np.full((5, 6), -2)
+    assert O.nnc_accept(a, a, center="raw").all()
+
+
+def test_frmc_offset_set_as_data():
+    """An FRMC offset set is data: the set [-r, r] is RMC of radius r (the
+    small range of the Fig. 2 caption, read as {-2,-1,0,1,2}), and any set
+    follows the brute-force loops; through motion_check the default set is
+    the paper's."""
+    rng = np.random.default_rng(8)
+    H, W = 14, 16
+    frames, _ = synth.video_translate_edges(2, H, W, rng, max_step=2)
+    mask = synth.fixed_mask(H, W, rng)
+    cur = synth.measured(frames[1], mask)
+    a, b, _, _ = O.forward_me(cur, mask, frames[0], 3)
+    b = b.copy()
+    b[6, 7] -= 2
+    small, _ = O.motion_check("frmc", cur, mask, frames[0], a, b, 3, frmc=(-2, -1, 0, 1, 2))
+    rmc2, _ = O.motion_check("rmc", cur, mask, frames[0], a, b, 3, rmc_radius=2)
+    assert np.array_equal(small, rmc2)
+    odd = (-5, -2, 0, 4)
+    acc, _ = O.motion_check("frmc", cur, mask, frames[0], a, b, 3, frmc=odd)
+    assert (acc == brute_rmc(cur, mask, frames[0], a, b, np.array(odd))).all()
+    dflt, _ = O.motion_check("frmc", cur, mask, frames[0], a, b, 3)
+    paper, _ = O.motion_check("frmc", cur, mask, frames[0], a, b, 3, frmc=(-7, -3, -1, 0, 1, 3, 7))
+    assert np.array_equal(dflt, paper)
+
+
+def test_support_crop_check_matches_whole_frame():
+    """The GPU tests' crop-based recomputation of a block support's motion
+    inputs (tests/_gpu.check_support_fields) reproduces the whole-frame
+    oracle, frame corners included, and catches a single changed decision."""
+    from _gpu import check_support_fields
+    rng = np.random.default_rng(21)
+    H, W, R = 96, 88, 9
+    frames = synth.video_regions(2, H, W, rng, grid=3, vmax=6)
+    mask = synth.mask_sequence("dynamic", 2, H, W, rng)[1]
+    cur = synth.measured(frames[1], mask)
+    recon = np.clip(frames[0].astype(int) + rng.integers(-5, 6, (H, W)), 0, 255).astype(np.uint8)
+    a, b, S, _ = O.forward_me(cur, mask, recon, R)
+    acc, _ = O.motion_check("nnc_frmc", cur, mask, recon, a, b, R)
+    blocks = [(0, 0), (H // 4 - 1, W // 4 - 1), (11, 10), (5, 0)]
+    assert check_support_fields(cur, mask, recon, a, b, acc, S, blocks, R) > 0
+    bad = acc.copy()
+    bad[44, 40] = ~bad[44, 40]
+    with pytest.raises(AssertionError):
+        check_support_fields(cur, mask, recon, a, b, bad, S, [(11, 10)], R)
