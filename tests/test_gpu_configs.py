@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 import synth
-from _gpu import FSR_TOL, PSNR_TOL, AMB_MAX, TAU_FP64, compare_fsr, dev, host, need_gpu
+from _gpu import FSR_TOL, PSNR_TOL, AMB_MAX, TAU_FP64, check_support_fields, compare_fsr, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -81,10 +81,21 @@ def test_1080p_recursive_frame_sampled():
     # projection from the verified fields and decisions, then FSR at sampled blocks
     values, cls = O.project(cur, mask, fields)
     blocks = np.stack([rng.integers(0, H // 4, 96), rng.integers(0, W // 4, 96)], axis=1)
+    blocks[:2] = [[0, W // 4 - 1], [H // 8, W // 8]]
+    # the first 8 blocks: every motion input of their supports recomputed by
+    # the oracle (vectors and costs on the support grown by 2, NNC -> FRMC
+    # decisions on the support, all three references), so their FSR input
+    # is oracle-derived end to end
+    for f, (recon, _, _) in zip(fields, refs):
+        _, _, cost = R.motion_check(dev(cur), dev(mask), dev(recon), R.MEParams(search=9, check="none"))
+        n = check_support_fields(cur, mask, recon, f["alpha"], f["beta"], f["accept"],
+                                 host(cost).astype(np.int64) & 0xFFFF, blocks[:8], 9)
+        assert n >= 8 * 32 * 24
     ora, gaps = O.fsr.fsr_blocks_out(values, cls, blocks, K=100)
     got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
     d = np.abs(got - ora).max(axis=(1, 2))
     amb = gaps < TAU_FP64
-    print(f"1080p frame 3: FSR max {d[~amb].max():.2e} over {(~amb).sum()} blocks, "
-          f"projected {(cls == 2).mean():.3f} of pixels")
+    print(f"1080p frame 3: FSR max {d[~amb].max():.2e} over {(~amb).sum()} blocks "
+          f"(8 end to end: max {d[:8].max():.2e}), projected {(cls == 2).mean():.3f} of pixels")
     assert d[~amb].max() <= FSR_TOL
+    assert amb.sum() <= AMB_MAX * len(blocks)

@@ -11,7 +11,7 @@ import torch
 
 import oracle as O
 import synth
-from _gpu import FSR_TOL, TAU_FP32, dev, host, need_gpu
+from _gpu import FSR_TOL, TAU_FP32, TAU_FP64, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -39,20 +39,29 @@ def test_mfma_dft_against_oracle_4k_sample(frame4k, K):
     nb = 256
     blocks = np.stack([rng.integers(0, H // 4, nb), rng.integers(0, W // 4, nb)], axis=1)
     ora, gaps = O.fsr.fsr_blocks_out(vals, m, blocks, K=K)
-    amb = gaps < TAU_FP32
     v_d, m_d = dev(vals, torch.float32), dev(m)
     res = {}
     for p in PRECS:
+        # the float64 kernel is held to the float64 near-tie threshold, the
+        # forms with float32 rounding (accumulation or residual) to the float32 one
+        amb = gaps < (TAU_FP64 if p == "fp64" else TAU_FP32)
         out, _ = R.fsr_blocks(v_d, m_d, R.FSRParams(iters=K, precision=p))
         d = block_errors(host(out), ora, blocks)
-        res[p] = d
+        res[p] = (d, amb)
         print(f"4K K={K} {p:7s}: max {d[~amb].max():.2e}  median {np.median(d[~amb]):.2e}  "
               f"blocks > 1e-3: {(d[~amb] > 1e-3).mean() * 100:.1f} %  (ambiguous {amb.sum()}/{nb})")
-    assert res["fp64"][~amb].max() <= FSR_TOL
+    d, amb = res["fp64"]
+    assert d[~amb].max() <= FSR_TOL and amb.sum() == 0
+    # measured shares of unambiguous sampled blocks beyond 1e-3 (K = 100 / 300):
+    # fp16x3 0 % / 1.6 %, bf16x3 5.9 % / 32.9 %, fp32 0 % / 0.4 %; the bounds
+    # allow about twice that
+    bound = {100: {"fp16x3": 0.0, "bf16x3": 0.12, "fp32": 0.01},
+             300: {"fp16x3": 0.04, "bf16x3": 0.50, "fp32": 0.02}}[K]
     for p in PRECS[1:]:
-        assert np.isfinite(res[p]).all()
-        # the split-operand DFT keeps the typical block far inside the 8-bit quantum
-        assert np.median(res[p][~amb]) < 0.05, p
+        d, amb = res[p]
+        assert np.isfinite(d).all()
+        assert (d[~amb] > 1e-3).mean() <= bound[p], p
+        assert np.median(d[~amb]) < 1e-3, p
 
 
 @pytest.mark.parametrize("K", [100, 300])
@@ -70,10 +79,8 @@ def test_mfma_dft_full_frame_psnr(K):
         d = np.abs(out - ora)
         dp = O.psnr(f[0], out, 8) - p_ora
         print(f"128x128 K={K} {p:7s}: max-abs {d.max():.3e}  PSNR {p_ora + dp:.4f} dB (delta {dp:+.4f})")
-        if p == "fp64":
-            assert abs(dp) <= 0.01
-        else:
-            assert abs(dp) < 0.5
+        # measured |delta| at most 0.016 dB (bf16x3, K = 300)
+        assert abs(dp) <= (0.01 if p == "fp64" else 0.05), p
 
 
 def test_mfma_dft_timing_1080p():
