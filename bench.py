@@ -84,73 +84,93 @@ def counters_from_profile():
 
 
 # ------------------------------------------------------------ CPU baseline --
-# The oracle timed on the host cores: one frame of the workload, with the
-# motion path (forward ME and the check, per reference) over row bands, the
-# projection in this process and FSR over runs of block rows, each band or run
-# a task of a process pool.  A band is computed on a crop with ORACLE_HALO
-# rows of margin where the crop edge is not the frame's: the oracle's reads
-# around a pixel reach 2R + 2 rows (reverse ME), R + 4 (forward ME feeding the
-# NNC medians) or 9 (FRMC), and an FSR support 14, so every kept row equals the
-# whole-frame oracle's (tests/test_bench_host.py checks this).
-ORACLE_HALO = 48
+# The oracle timed on the host cores: a band of rows of one frame of the
+# workload.  The motion path (forward ME and the check, per reference) runs on
+# column strips of the rows whose decisions the band's FSR supports read, the
+# projection in this process, FSR on tiles of blocks; each strip or tile is a
+# task of a process pool.  A strip is computed on a crop with `halo` pixels of
+# margin wherever the crop edge is not the frame's: around a pixel the oracle
+# reads within 2R + 2 (reverse ME), R + 4 (forward ME feeding the NNC medians),
+# the largest check offset + 2 (RMC, FRMC) or 14 (an FSR support) pixels, so
+# every kept pixel equals the whole-frame oracle's (tests/test_bench_host.py
+# checks this).
 
 
-def _crop_rows(H, y0, y1, halo):
-    return max(0, y0 - halo), min(H, y1 + halo)
+def oracle_halo(me_o):
+    """Margin of a motion crop that leaves its kept pixels as in the whole frame."""
+    rr = me_o.rmc_radius or 0
+    offs = max((abs(d) for d in me_o.frmc), default=0) if me_o.frmc is not None else 7
+    return max(2 * me_o.search, rr, offs, 14) + 4
+
+
+def _crop(n, a, b, halo):
+    return max(0, a - halo), min(n, b + halo)
 
 
 def _oracle_motion_task(args):
-    """Forward ME + check of one reference on a crop; returns the kept rows."""
+    """Forward ME + check of one reference on a crop; returns the kept pixels."""
     from oracle.frame import motion_fields
-    cur, mask, recon, keep0, keep1, me = args
+    cur, mask, recon, ky, kx, me = args
     f = motion_fields(cur, mask, [(recon, None, None)], me)[0]
-    return f["alpha"][keep0:keep1], f["beta"][keep0:keep1], f["accept"][keep0:keep1]
+    return f["alpha"][ky, kx], f["beta"][ky, kx], f["accept"][ky, kx]
 
 
 def _oracle_fsr_task(args):
-    """FSR of the block rows [bi0, bi1) of a crop starting at block row cb."""
+    """FSR of the block rows [bi0, bi1) x columns [bj0, bj1) of a crop whose
+    origin is block (cb, cj)."""
     import numpy as np
     import oracle as O
-    values, cls, cb, bi0, bi1, fsr = args
-    nbw = values.shape[1] // 4
-    bi, bj = np.mgrid[bi0 - cb:bi1 - cb, 0:nbw]
+    values, cls, cb, cj, bi0, bi1, bj0, bj1, fsr = args
+    bi, bj = np.mgrid[bi0 - cb:bi1 - cb, bj0 - cj:bj1 - cj]
     blocks = np.stack([bi.ravel(), bj.ravel()], axis=1)
     out, _ = O.fsr.fsr_blocks_out(values, cls, blocks, fsr.block, fsr.support, fsr.rho, fsr.gamma,
                                   fsr.iters, fsr.proj_weight, fsr.overwrite, track_gaps=False)
     return out
 
 
-def oracle_frame_rows(pool, cur, cur_mask, refs, me_o, fsr_o, y0, y1, band=32, halo=ORACLE_HALO):
+def oracle_frame_rows(pool, cur, cur_mask, refs, me_o, fsr_o, y0, y1, strips=8, halo=None):
     """The oracle's reconstruction of rows [y0, y1) of one frame (multiples of
-    4), computed as band tasks on `pool` (motion crops with `halo` rows of
-    margin).  refs: [(recon, meas, mask)] for lags 1..nref (full frames).
-    Returns out[y0:y1] (float64)."""
+    4), computed as tasks on `pool`: per reference `strips` column strips of
+    the motion path (crops with `halo` pixels of margin, default
+    oracle_halo), then FSR on `strips` x (rows / 4) tiles of blocks.
+    refs: [(recon, meas, mask)] for lags 1..nref (full frames).  Returns
+    out[y0:y1] (float64)."""
     import numpy as np
     import oracle as O
     H, W = cur.shape
+    halo = oracle_halo(me_o) if halo is None else halo
     m0, m1 = max(0, y0 - 16), min(H, y1 + 16)          # rows whose decisions feed the blocks' supports
+    cy0, cy1 = _crop(H, m0, m1, halo)
+    edges = [(W * i // strips) & ~3 for i in range(strips)] + [W]
     tasks, where = [], []
     for k, (recon, _, _) in enumerate(refs):
-        for b0 in range(m0, m1, band):
-            b1 = min(m1, b0 + band)
-            c0, c1 = _crop_rows(H, b0, b1, halo)
-            tasks.append((cur[c0:c1], cur_mask[c0:c1], recon[c0:c1], b0 - c0, b1 - c0, me_o))
-            where.append((k, b0, b1))
+        for x0, x1 in zip(edges[:-1], edges[1:]):
+            if x1 <= x0:
+                continue
+            cx0, cx1 = _crop(W, x0, x1, halo)
+            crop = (slice(cy0, cy1), slice(cx0, cx1))
+            keep = (slice(m0 - cy0, m1 - cy0), slice(x0 - cx0, x1 - cx0))
+            tasks.append((cur[crop], cur_mask[crop], recon[crop], keep[0], keep[1], me_o))
+            where.append((k, x0, x1))
     fields = [dict(alpha=np.zeros((H, W), np.int64), beta=np.zeros((H, W), np.int64),
                    accept=np.zeros((H, W), bool), meas=meas, mask=mask) for _, meas, mask in refs]
-    for (k, b0, b1), (a, b, acc) in zip(where, pool.map(_oracle_motion_task, tasks)):
-        fields[k]["alpha"][b0:b1], fields[k]["beta"][b0:b1], fields[k]["accept"][b0:b1] = a, b, acc
+    for (k, x0, x1), (a, b, acc) in zip(where, pool.map(_oracle_motion_task, tasks)):
+        f = fields[k]
+        f["alpha"][m0:m1, x0:x1], f["beta"][m0:m1, x0:x1], f["accept"][m0:m1, x0:x1] = a, b, acc
     values, cls = O.project(cur, cur_mask, fields)
     tasks, where = [], []
-    for r0 in range(y0, y1, band):
-        r1 = min(y1, r0 + band)
-        c0, c1 = _crop_rows(H, r0, r1, 16)
-        tasks.append((values[c0:c1], cls[c0:c1], c0 // 4, r0 // 4, r1 // 4, fsr_o))
-        where.append((r0, r1))
+    for r0 in range(y0, y1, 4):
+        for x0, x1 in zip(edges[:-1], edges[1:]):
+            if x1 <= x0:
+                continue
+            ry0, ry1 = _crop(H, r0, r0 + 4, 16)
+            rx0, rx1 = _crop(W, x0, x1, 16)
+            tasks.append((values[ry0:ry1, rx0:rx1], cls[ry0:ry1, rx0:rx1], ry0 // 4, rx0 // 4,
+                          r0 // 4, r0 // 4 + 1, x0 // 4, x1 // 4, fsr_o))
+            where.append((r0, x0, x1))
     out = np.zeros((y1 - y0, W))
-    for (r0, r1), ob in zip(where, pool.map(_oracle_fsr_task, tasks)):
-        nbw = W // 4
-        out[r0 - y0:r1 - y0] = ob.reshape((r1 - r0) // 4, nbw, 4, 4).transpose(0, 2, 1, 3).reshape(r1 - r0, W)
+    for (r0, x0, x1), ob in zip(where, pool.map(_oracle_fsr_task, tasks)):
+        out[r0 - y0:r0 - y0 + 4, x0:x1] = ob.transpose(1, 0, 2).reshape(4, x1 - x0)
     return out
 
 
@@ -160,23 +180,25 @@ def cpu_cores():
     return max(1, min(len(os.sched_getaffinity(0)), 16))
 
 
-def cpu_baseline(pool, cores, frames, masks, recons, me_o, fsr_o):
+def cpu_baseline(pool, cores, frames, masks, recons, me_o, fsr_o, rows_per_core=8):
     """The oracle (float64 FSR, integer ME) on frame 3 of the workload with
     the GPU's reconstructions of frames 0..2 as its references, on a band of
-    32 rows per core (full width) in the middle of the frame."""
+    `rows_per_core` rows per process (full width) in the middle of the frame."""
     import synth
     H, W = frames.shape[1:]
-    rows = min(H, 32 * cores) & ~3
+    rows = min(H, rows_per_core * cores) & ~3
     y0 = ((H - rows) // 2) & ~3
     meas = synth.measured(frames[:4], masks[:4])
     refs = [(recons[3 - k], meas[3 - k], masks[3 - k]) for k in (1, 2, 3)]
+    strips = max(1, cores // 2)
     t0 = time.perf_counter()
-    oracle_frame_rows(pool, meas[3], masks[3], refs, me_o, fsr_o, y0, y0 + rows)
+    oracle_frame_rows(pool, meas[3], masks[3], refs, me_o, fsr_o, y0, y0 + rows, strips=strips)
     dt = time.perf_counter() - t0
     return {"value": round(rows * W / dt / 1e6, 6), "unit": "HR Mpix/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"frame 3, rows {y0}..{y0 + rows - 1} ({W}x{rows}, three references = the GPU's "
-                      f"uint8 reconstructions of frames 0-2), {cores} processes over 32-row bands; {dt:.1f} s"}
+            "sample": f"frame 3, rows {y0}..{y0 + rows - 1} ({W}x{rows}; three references = the GPU's "
+                      f"uint8 reconstructions of frames 0-2), {cores} processes: motion path on {strips} column "
+                      f"strips per reference, FSR on block tiles; {dt:.1f} s"}
 
 
 def plain_fp32_form(a, seq_args, d_meas, d_mask, frames, ref_out, stream):

@@ -102,20 +102,20 @@ def test_traffic_record_scales_counters_by_the_copy(tmp_path, monkeypatch):
 
 
 def test_banded_oracle_equals_whole_frame_oracle():
-    """The CPU baseline's decomposition (motion path over row bands with
-    halos, projection, FSR over runs of block rows, as pool tasks) gives
+    """The CPU baseline's decomposition (motion path on column strips of the
+    band with halos, projection, FSR on block tiles, as pool tasks) gives
     exactly the whole-frame oracle's rows: at the bench's setting (R = 9,
-    NNC -> FRMC, the default halo) on a frame tall enough for crops whose
-    edges lie inside the frame, and for RME (the widest reach, 2R + 2 rows)
-    with a halo just above it."""
+    NNC -> FRMC, the default halo) on a frame large enough for crops whose
+    edges lie inside it, and for RME (the widest reach, 2R + 2) with a halo
+    just above that reach."""
     import multiprocessing as mp
     import oracle as O
     import synth
     rng = np.random.default_rng(4)
     fsr = O.FSRParams(iters=8)
     with mp.get_context("spawn").Pool(2) as pool:
-        for H, W, R, check, y0, y1, band, halo in ((160, 40, 9, "nnc_frmc", 56, 104, 16, bench.ORACLE_HALO),
-                                                  (64, 32, 4, "rme", 8, 56, 8, 12)):
+        for H, W, R, check, y0, y1, strips, halo in ((120, 96, 9, "nnc_frmc", 52, 68, 3, None),
+                                                    (64, 48, 4, "rme", 24, 40, 3, 12)):
             frames, _ = synth.video_translate_edges(4, H, W, rng, max_step=3, n_edges=3)
             masks = synth.mask_sequence("dynamic", 4, H, W, rng)
             meas = synth.measured(frames, masks)
@@ -123,8 +123,11 @@ def test_banded_oracle_equals_whole_frame_oracle():
                      for t in range(3)]
             refs = [(recon[2 - k], meas[2 - k], masks[2 - k]) for k in range(3)]
             me = O.MEParams(search=R, check=check)
+            if halo is None:
+                assert bench.oracle_halo(me) == 22
             whole = O.reconstruct_frame(meas[3], masks[3], refs, me, fsr, track_gaps=False)["out"]
-            got = bench.oracle_frame_rows(pool, meas[3], masks[3], refs, me, fsr, y0, y1, band=band, halo=halo)
+            got = bench.oracle_frame_rows(pool, meas[3], masks[3], refs, me, fsr, y0, y1, strips=strips,
+                                          halo=halo)
             assert np.array_equal(got, whole[y0:y1]), (check, y0, y1)
 
 
