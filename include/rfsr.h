@@ -128,6 +128,10 @@ typedef struct {
     double concealed_weight; /* delta, 0 <= delta <= 1 (0 = independent blocks) */
     double prior_sigma;  /* frequency-weighting prior, 0 (off) or 0 < sigma <= 1 */
     double stop_ratio;   /* residual-energy early stop, 0 (off) or 0 < ratio < 1 */
+    double mixed_bound;  /* RFSR_PREC_MIXED: near-tie bound a > 0 (below)    */
+    float* block_margin; /* RFSR_PREC_FP32, nullable: per-block margins (below) */
+    unsigned long long* rerun_blocks; /* RFSR_PREC_MIXED, nullable: device
+                            counter, ADDED the number of blocks recomputed   */
 } rfsr_fsr_params;
 
 /* Basis selection.  pairs = 0 (default): every iteration adds one complex
@@ -175,7 +179,9 @@ typedef struct {
  *            plain float32 form).  Complex single bins and independent
  *            blocks only (pairs, concealed_weight > 0 and the literature
  *            options give RFSR_EUNSUPPORTED).
- * The forms other than FP64 trade accuracy (float32 accumulation, ~2^-16 /
+ *   MIXED    FP32 with a near-tie test and float64 for the blocks that fail
+ *            it (below); held to the float64 form's tolerance.
+ * BF16X3, FP16X3 and FP32 trade accuracy (float32 accumulation, ~2^-16 /
  * ~2^-22 operand splits, float32 rounding of the residual) for throughput;
  * they are not bit-compatible with FP64 and are not held to its 1e-3 output
  * tolerance: they exist to quantify that trade. */
@@ -183,8 +189,34 @@ typedef enum {
     RFSR_PREC_FP64 = 0,
     RFSR_PREC_BF16X3 = 1,
     RFSR_PREC_FP16X3 = 2,
-    RFSR_PREC_FP32 = 3
+    RFSR_PREC_FP32 = 3,
+    RFSR_PREC_MIXED = 4
 } rfsr_precision;
+
+/* RFSR_PREC_MIXED: the float32 form with a near-tie test, and float64 for
+ * the blocks that fail it, so that every block follows the float64 model.
+ * The float32 residual differs from the float64 one by rounding of the order
+ * of u ||R^0||_2 in every bin (u = 2^-24, R^0 the block's initial weighted
+ * residual spectrum; the FFT's rounding dominates and the updates add little),
+ * so a float32 pick can differ from the float64 model's only where the pick's
+ * energy E_b and the largest other energy E_next (not counting, while the
+ * spectrum is still Hermitian, the pick's conjugate partner, which ties
+ * exactly and leads to the same real model) are that close.  A block is
+ * recomputed by the float64 kernel if at some iteration
+ *     E_b - E_next <= 4 a u ||R^0||_2 |R_b|      (a = mixed_bound)
+ * i.e. |R_b| - |R_next| below about 2 a u ||R^0||_2; the float32 pass of such
+ * a block stops there.  Complex single bins and independent blocks only, as
+ * FP32.  RFSR_MIXED_BOUND is the bound the library is measured with: the
+ * flips of the plain float32 form were all found at margins far below it.
+ *
+ * block_margin (RFSR_PREC_FP32 only, a diagnostic that calibrates a): device
+ * float per block of the call (flat block index, row-major per frame, frames
+ * in call order), receiving the smallest (E_b - E_next) / (4 u ||R^0||_2 |R_b|)
+ * over the block's iterations; RFSR_PREC_MIXED with bound a recomputes
+ * exactly the blocks whose margin is at most a.  Ignored by other precisions.
+ * rerun_blocks (RFSR_PREC_MIXED only): device counter the call adds the
+ * number of recomputed blocks to; nullable. */
+#define RFSR_MIXED_BOUND 1.0
 
 /* Indices into the optional counters array of rfsr_motion_check. */
 enum {
@@ -240,9 +272,11 @@ rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32
 /* fsr_blocks without a workspace argument, for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation.  The call allocates nothing; its scratch (the FSR
- * tables, 17 KB) lives in an array inside the library of
- * RFSR_NOALLOC_SCRATCH_BYTES per device, which every device that runs the
- * library holds until the process ends.  All calls on one device share that
+ * tables, 17 KB, and for RFSR_PREC_MIXED the list of blocks to recompute,
+ * 4 bytes per block + 256) lives in an array inside the library of
+ * RFSR_NOALLOC_SCRATCH_BYTES per device (enough for the mixed form up to
+ * about a million blocks, i.e. 16 megapixels), which every device that runs
+ * the library holds until the process ends.  All calls on one device share that
  * device's array: calls that overlap on one device (different streams or
  * threads) race, and the caller must serialise them.  The array keeps the
  * last call's contents; nothing in it needs to start at zero (each call
@@ -250,7 +284,7 @@ rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32
  * Errors: as fsr_blocks; RFSR_EWORKSPACE if the request needs more scratch
  * than the array holds; RFSR_EDEVICE if the array's device address cannot be
  * obtained on the current device. */
-#define RFSR_NOALLOC_SCRATCH_BYTES 32768
+#define RFSR_NOALLOC_SCRATCH_BYTES 4194304
 rfsr_status fsr_blocks_noalloc(const float* values, const uint8_t* cls, int32_t H, int32_t W,
                                int64_t pitch, const rfsr_fsr_params* fsr,
                                float* out, uint8_t* out_u8, void* stream);

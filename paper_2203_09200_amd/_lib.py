@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "librfsr.so")
 
 CHECKS = {"none": 0, "rme": 1, "rmc": 2, "frmc": 3, "nnc": 4, "nnc_frmc": 5}
 OVERWRITE = {"dfsr": 0, "rfsr": 1}
-PRECISION = {"fp64": 0, "bf16x3": 1, "fp16x3": 2, "fp32": 3}
+PRECISION = {"fp64": 0, "bf16x3": 1, "fp16x3": 2, "fp32": 3, "mixed": 4}
+MIXED_BOUND = 1.0   # RFSR_MIXED_BOUND
 NCOUNTERS = 4
 COUNTER_NAMES = ("forward_costs", "check_costs", "checked_pixels", "accepted")
 
@@ -40,7 +41,9 @@ class _FSRParams(ctypes.Structure):
                 ("rho", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("proj_weight", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("pairs", ctypes.c_int32), ("concealed_weight", ctypes.c_double),
-                ("prior_sigma", ctypes.c_double), ("stop_ratio", ctypes.c_double)]
+                ("prior_sigma", ctypes.c_double), ("stop_ratio", ctypes.c_double),
+                ("mixed_bound", ctypes.c_double), ("block_margin", ctypes.c_void_p),
+                ("rerun_blocks", ctypes.c_void_p)]
 
 
 NNC_CENTER = {"filtered": 0, "raw": 1}
@@ -79,16 +82,28 @@ class FSRParams:
     overwrite: str = "dfsr"
     block: int = 4
     support: int = 32
-    precision: str = "fp64"     # "fp64"; block DFT "bf16x3" or "fp16x3" (matrix cores); "fp32" (all float32)
+    precision: str = "fp64"     # "fp64"; block DFT "bf16x3" or "fp16x3" (matrix cores); "fp32" (all float32);
+                                # "mixed" (float32 with a near-tie test, float64 for the blocks that fail it)
     concealed_weight: float = 0.0   # delta > 0: raster-order blocks (wavefront), single frames only
     pairs: bool = False             # real-valued FSR: conjugate pairs per iteration
     prior_sigma: float = 0.0        # frequency-weighting prior (0: off)
     stop_ratio: float = 0.0         # residual-energy early stop (0: off)
+    mixed_bound: float = MIXED_BOUND    # "mixed": near-tie bound a
+    block_margin: object = None     # "fp32": float32 device tensor, one margin per block (diagnostic)
+    rerun_blocks: object = None     # "mixed": int64 device tensor (1 element) the call adds its recomputed blocks to
 
     def c(self) -> _FSRParams:
+        for t, dt, nm in ((self.block_margin, torch.float32, "block_margin"),
+                          (self.rerun_blocks, torch.int64, "rerun_blocks")):
+            if t is not None and (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt
+                                  or not t.is_contiguous()):
+                raise RfsrError(f"{nm}: expected a contiguous {dt} device tensor")
         return _FSRParams(self.block, self.support, self.iters, OVERWRITE[self.overwrite],
                           self.rho, self.gamma, self.proj_weight, PRECISION[self.precision],
-                          int(self.pairs), self.concealed_weight, self.prior_sigma, self.stop_ratio)
+                          int(self.pairs), self.concealed_weight, self.prior_sigma, self.stop_ratio,
+                          self.mixed_bound,
+                          None if self.block_margin is None else self.block_margin.data_ptr(),
+                          None if self.rerun_blocks is None else self.rerun_blocks.data_ptr())
 
 
 class FrameDesc(ctypes.Structure):

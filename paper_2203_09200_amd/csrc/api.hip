@@ -58,13 +58,15 @@ rfsr_status check_fsr(const rfsr_fsr_params* p) {
     if (!(p->proj_weight >= 0.0) || !isfinite(p->proj_weight)) return RFSR_EINVAL;
     if (p->overwrite != RFSR_DFSR && p->overwrite != RFSR_RFSR) return RFSR_EINVAL;
     if (p->block < 1 || p->support < p->block) return RFSR_EINVAL;
-    if (p->precision < RFSR_PREC_FP64 || p->precision > RFSR_PREC_FP32) return RFSR_EINVAL;
+    if (p->precision < RFSR_PREC_FP64 || p->precision > RFSR_PREC_MIXED) return RFSR_EINVAL;
+    if (p->precision == RFSR_PREC_MIXED && !(p->mixed_bound > 0.0 && p->mixed_bound <= 1e6)) return RFSR_EINVAL;
     if (!(p->concealed_weight >= 0.0 && p->concealed_weight <= 1.0)) return RFSR_EINVAL;
     if (p->pairs != 0 && p->pairs != 1) return RFSR_EINVAL;
     if (!(p->prior_sigma >= 0.0 && p->prior_sigma <= 1.0)) return RFSR_EINVAL;
     if (!(p->stop_ratio >= 0.0 && p->stop_ratio < 1.0)) return RFSR_EINVAL;
     if (p->pairs && p->concealed_weight > 0.0) return RFSR_EUNSUPPORTED;
-    if (p->precision == RFSR_PREC_FP32 && (p->pairs || p->concealed_weight > 0.0)) return RFSR_EUNSUPPORTED;
+    const bool f32 = p->precision == RFSR_PREC_FP32 || p->precision == RFSR_PREC_MIXED;
+    if (f32 && (p->pairs || p->concealed_weight > 0.0)) return RFSR_EUNSUPPORTED;
     if ((p->prior_sigma > 0.0 || p->stop_ratio > 0.0) &&
         (p->pairs || p->concealed_weight > 0.0 || p->precision != RFSR_PREC_FP64))
         return RFSR_EUNSUPPORTED;
@@ -106,9 +108,11 @@ struct FrameScratch {
     }
 };
 
-// Workspace of the single-frame entry points: FSR tables | frame scratch.
+// Workspace of the single-frame entry points: FSR tables | the mixed form's
+// recomputation list | frame scratch.
 size_t single_ws(int H, int W, int nref) {
-    return align256(sizeof(FsrTables)) + FrameScratch(H, W, nref).bytes;
+    return align256(sizeof(FsrTables)) + rerun_bytes((size_t)(H / kBlock) * (W / kBlock)) +
+           FrameScratch(H, W, nref).bytes;
 }
 
 // One frame to reconstruct; rfsr_frame_desc and the single-frame arguments
@@ -231,17 +235,22 @@ rfsr_status check_batch(const rfsr_frame_desc* d, int n) {
     return RFSR_OK;
 }
 
-// Workspace of a batch: FSR tables | scratch of frame 0 | frame 1 | ...
+// Workspace of a batch: FSR tables | the mixed form's recomputation list
+// (every block of the batch) | scratch of frame 0 | frame 1 | ...
 // Job-table image: header | FrameJob[n] | RefJob[total references].
 struct BatchLayout {
     int nrefs = 0;
     size_t table_bytes, refs_offset, total;
     std::vector<size_t> frame_base;
     BatchLayout(const rfsr_frame_desc* d, int n) : frame_base(n) {
-        for (int i = 0; i < n; ++i) nrefs += d[i].nref;
+        size_t blocks = 0;
+        for (int i = 0; i < n; ++i) {
+            nrefs += d[i].nref;
+            blocks += (size_t)(d[i].H / kBlock) * (d[i].W / kBlock);
+        }
         refs_offset = kTableHeader + sizeof(FrameJob) * (size_t)n;
         table_bytes = align256(refs_offset + sizeof(RefJob) * (size_t)nrefs);
-        size_t o = align256(sizeof(FsrTables));
+        size_t o = align256(sizeof(FsrTables)) + rerun_bytes(blocks);
         for (int i = 0; i < n; ++i) {
             frame_base[i] = o;
             o += FrameScratch(d[i].H, d[i].W, d[i].nref).bytes;
@@ -405,6 +414,7 @@ hipError_t run_batch(const rfsr_frame_desc* frames, int n, const rfsr_me_params&
     const Jobs<FrameJob> jf = table<FrameJob>(img, kTableHeader, n, key);
     const Jobs<RefJob> jr = table<RefJob>(img, L.refs_offset, (int)p.refs.size(), key);
     FsrTables* tab = reinterpret_cast<FsrTables*>(ws);
+    unsigned* rerun = reinterpret_cast<unsigned*>(ws + align256(sizeof(FsrTables)));
     hipError_t e = hipSuccess;
     auto record = [&](int k) {
         if (stage_events && e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(stage_events[k]), s);
@@ -415,7 +425,7 @@ hipError_t run_batch(const rfsr_frame_desc* frames, int n, const rfsr_me_params&
                            reinterpret_cast<uint32_t*>(const_cast<uint8_t*>(img)));
         e = hipGetLastError();
     }
-    if (e == hipSuccess && part.finish()) e = launch_fsr_tables(tab, fsr->rho, fsr->prior_sigma, s);
+    if (e == hipSuccess && part.finish()) e = launch_fsr_tables(tab, fsr->rho, fsr->prior_sigma, s, rerun);
     if (e == hipSuccess && !p.refs.empty()) {
         e = launch_windows(jf, p.win, s);
         if (e == hipSuccess) e = launch_motion(jr, p.tiles, p.px_refs, p.frmc, me, nullptr, s);
@@ -423,7 +433,7 @@ hipError_t run_batch(const rfsr_frame_desc* frames, int n, const rfsr_me_params&
     record(1);
     if (e == hipSuccess && part.finish()) e = launch_project(jf, p.px_frames, s);
     record(2);
-    if (e == hipSuccess && part.finish()) e = launch_fsr(jf, p.blocks, *fsr, tab, s, p.frames.data());
+    if (e == hipSuccess && part.finish()) e = launch_fsr(jf, p.blocks, *fsr, tab, s, p.frames.data(), rerun);
     record(3);
     return e;
 }
@@ -499,8 +509,12 @@ rfsr_status static_scratch(void** p) {
     return RFSR_OK;
 }
 
-// Scratch bytes of one fsr_blocks call (the FSR tables).
-size_t fsr_blocks_scratch_bytes() { return align256(sizeof(FsrTables)); }
+// Scratch bytes of one fsr_blocks call: the FSR tables, and for the mixed
+// form the recomputation list.
+size_t fsr_blocks_scratch_bytes(int H, int W, int precision) {
+    return align256(sizeof(FsrTables)) +
+           (precision == RFSR_PREC_MIXED ? rerun_bytes((size_t)(H / kBlock) * (W / kBlock)) : 0);
+}
 
 rfsr_status check_blocks_args(const float* values, const uint8_t* cls, int32_t H, int32_t W, int64_t pitch,
                               const rfsr_fsr_params* fsr, const float* out) {
@@ -515,10 +529,13 @@ rfsr_status run_fsr_blocks(const float* values, const uint8_t* cls, int32_t H, i
                            const rfsr_fsr_params& fsr_p, float* out, uint8_t* out_u8, void* workspace,
                            size_t ws_bytes, void* stream) {
     const rfsr_fsr_params* fsr = &fsr_p;
-    rfsr_status st = check_ws(workspace, ws_bytes, fsr_blocks_scratch_bytes());
+    rfsr_status st = check_ws(workspace, ws_bytes, fsr_blocks_scratch_bytes(H, W, fsr->precision));
     if (st != RFSR_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     FsrTables* tab = static_cast<FsrTables*>(workspace);
+    unsigned* rerun = fsr->precision == RFSR_PREC_MIXED
+                          ? reinterpret_cast<unsigned*>(static_cast<uint8_t*>(workspace) + align256(sizeof(FsrTables)))
+                          : nullptr;
     FrameJob fj;
     memset(&fj, 0, sizeof(fj));
     fj.values = const_cast<float*>(values);   // read only by the FSR kernel
@@ -530,8 +547,8 @@ rfsr_status run_fsr_blocks(const float* values, const uint8_t* cls, int32_t H, i
     fj.vpitch = pitch;
     fj.H = H;
     fj.W = W;
-    hipError_t e = launch_fsr_tables(tab, fsr->rho, fsr->prior_sigma, s);
-    if (e == hipSuccess) e = launch_fsr(single(fj), (H / kBlock) * (W / kBlock), *fsr, tab, s);
+    hipError_t e = launch_fsr_tables(tab, fsr->rho, fsr->prior_sigma, s, rerun);
+    if (e == hipSuccess) e = launch_fsr(single(fj), (H / kBlock) * (W / kBlock), *fsr, tab, s, nullptr, rerun);
     return from_hip(e);
 }
 
@@ -600,7 +617,7 @@ rfsr_status fsr_blocks_noalloc(const float* values, const uint8_t* cls, int32_t 
                                const rfsr_fsr_params* fsr, float* out, uint8_t* out_u8, void* stream) {
     rfsr_status st = check_blocks_args(values, cls, H, W, pitch, fsr, out);
     if (st != RFSR_OK) return st;
-    if (fsr_blocks_scratch_bytes() > kStaticScratch) return RFSR_EWORKSPACE;
+    if (fsr_blocks_scratch_bytes(H, W, fsr->precision) > kStaticScratch) return RFSR_EWORKSPACE;
     void* ws = nullptr;
     if ((st = static_scratch(&ws)) != RFSR_OK) return st;
     return run_fsr_blocks(values, cls, H, W, pitch, *fsr, out, out_u8, ws, kStaticScratch, stream);

@@ -78,6 +78,19 @@ __device__ __forceinline__ int xcd_remap(int g, int n) {
 // ------------------------------------------------------------ workspaces --
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Scratch of the mixed-precision FSR: the number of blocks the float32 pass
+// listed for recomputation (first 256 bytes), then their flat indices.
+__host__ __device__ inline size_t rerun_bytes(size_t blocks) { return 256 + align256(4 * blocks); }
+constexpr size_t kRerunList = 256;
+
+// Arguments of the float32 kernel's mixed and diagnostic modes.
+struct MixedArgs {
+    float bound;          // near-tie bound a (units of 2^-24 ||R^0||_2)
+    unsigned* count;      // listed blocks
+    int* list;            // their flat block indices
+    float* margins;       // diagnostic: per-block smallest margin
+};
+
 // Tables used by the FSR kernel (written by fsr_tables_kernel).
 struct FsrTables {
     double rho[kSupport * kSupport];    // rho ** distance to the support centre
@@ -221,15 +234,21 @@ __host__ __device__ inline int frmc_groups(int H, int W) { return (H * W + kFrmc
 
 // --------------------------------------------------------------- launches --
 // Each returns hipSuccess or the launch error.
-hipError_t launch_fsr_tables(FsrTables* t, double rho, double prior_sigma, hipStream_t s);
+// The FSR tables; also zeroes the mixed form's counter at `rerun` (nullable).
+hipError_t launch_fsr_tables(FsrTables* t, double rho, double prior_sigma, hipStream_t s,
+                             unsigned* rerun = nullptr);
 // FSR over all `total_blocks` blocks of the frames in `js`.  With a
 // concealed weighting and a job table, `host_frames` is the host copy of the
-// table (frame sizes for the wavefront grid).
+// table (frame sizes for the wavefront grid).  The mixed form needs `rerun`,
+// rerun_bytes(total_blocks) of scratch whose counter the tables launch zeroed.
 hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
-                      const FsrTables* tables, hipStream_t s, const FrameJob* host_frames = nullptr);
-// The float32 form (precision RFSR_PREC_FP32; independent blocks, complex bins).
+                      const FsrTables* tables, hipStream_t s, const FrameJob* host_frames = nullptr,
+                      unsigned* rerun = nullptr);
+// The float32 kernel (precision RFSR_PREC_FP32 and the float32 pass of
+// RFSR_PREC_MIXED; independent blocks, complex bins): mode 0 plain, 1 the
+// mixed form's pass, 2 plain with per-block margins (`mx`).
 hipError_t launch_fsr_f32(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
-                          const FsrTables* tables, hipStream_t s);
+                          const FsrTables* tables, hipStream_t s, const MixedArgs& mx, int mode);
 
 // Window planes of the frames in `js` (frames with fm == nullptr skipped).
 hipError_t launch_windows(const Jobs<FrameJob>& js, int total_groups, hipStream_t s);

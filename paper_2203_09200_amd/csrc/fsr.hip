@@ -244,8 +244,9 @@ __device__ __forceinline__ void dft_mfma(const double (&xs)[16], const double (&
 
 }  // namespace
 
-__global__ void fsr_tables_kernel(FsrTables* t, double rho, double sigma) {
+__global__ void fsr_tables_kernel(FsrTables* t, double rho, double sigma, unsigned* rerun) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && rerun) *rerun = 0u;   // the mixed form's list starts empty
     if (i < kSupport * kSupport) {
         const double dm = (i >> 5) - 15.5, dn = (i & 31) - 15.5;
         t->rho[i] = pow(rho, sqrt(dm * dm + dn * dn));
@@ -283,11 +284,25 @@ __global__ void fsr_tables_kernel(FsrTables* t, double rho, double sigma) {
 // OPT (float64 FFT, independent blocks, complex bins only): bit 0 weighs the
 // pick's energies with the frequency prior of `tab`, bit 1 stops a block once
 // its pick's (weighted) energy falls below stop_ratio times its first.
-template <int PREC, bool CONC, bool PAIRS, int OPT = 0>
+//
+// RERUN (the mixed form's float64 recomputation): workgroup i takes the
+// block rerun[kRerunList / 4 + i] of the list the float32 pass wrote, if i is
+// below the list's length rerun[0]; the grid covers every block, and the
+// workgroups beyond the length return at once.
+template <int PREC, bool CONC, bool PAIRS, int OPT = 0, bool RERUN = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void fsr_block_kernel(
     Jobs<FrameJob> js, int total, const FsrTables* __restrict__ tab, int K, double gamma,
-    double projw, int overwrite, double delta, int step, int bi0, double stop_ratio) {
+    double projw, int overwrite, double delta, int step, int bi0, double stop_ratio,
+    const unsigned* __restrict__ rerun, unsigned long long* rerun_stats) {
     static_assert(OPT == 0 || (PREC == RFSR_PREC_FP64 && !CONC && !PAIRS), "options: plain loop only");
+    static_assert(!RERUN || (PREC == RFSR_PREC_FP64 && !CONC && !PAIRS && OPT == 0), "rerun: plain loop");
+    int gb_rerun = 0;
+    if constexpr (RERUN) {
+        const unsigned n = *(const_ptr<unsigned>)(uintptr_t)rerun;
+        if (blockIdx.x >= n) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && rerun_stats) atomicAdd(rerun_stats, (unsigned long long)n);
+        gb_rerun = (int)(*(const_ptr<unsigned>)(uintptr_t)(rerun + kRerunList / 4 + blockIdx.x));
+    }
     constexpr bool PRIOR = (OPT & 1) != 0, STOP = (OPT & 2) != 0;
     // W table (32 x 32 complex double); the transpose planes reuse it.  Static,
     // so its LDS base folds into the read addresses.  The (bin, dlt) list of
@@ -309,7 +324,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         s_tw[2 * lane + 1] = tw[2 * lane + 1];
     }
 
-    const int gb = CONC ? 0 : xcd_remap(blockIdx.x, total);
+    const int gb = RERUN ? gb_rerun : (CONC ? 0 : xcd_remap(blockIdx.x, total));
     {
         int wbi = 0;
         const FrameJob fj = CONC ? wave_job(js, step, bi0, wbi) : job_at(js, gb, &FrameJob::g_blk);
@@ -542,13 +557,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     }
 }
 
-hipError_t launch_fsr_tables(FsrTables* t, double rho, double prior_sigma, hipStream_t s) {
-    hipLaunchKernelGGL(fsr_tables_kernel, dim3(4), dim3(256), 0, s, t, rho, prior_sigma);
+hipError_t launch_fsr_tables(FsrTables* t, double rho, double prior_sigma, hipStream_t s, unsigned* rerun) {
+    hipLaunchKernelGGL(fsr_tables_kernel, dim3(4), dim3(256), 0, s, t, rho, prior_sigma, rerun);
     return hipGetLastError();
 }
 
 hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
-                      const FsrTables* tables, hipStream_t s, const FrameJob* host_frames) {
+                      const FsrTables* tables, hipStream_t s, const FrameJob* host_frames, unsigned* rerun) {
     if (total_blocks <= 0) return hipSuccess;
     const size_t shmem = sizeof(float4) * (size_t)p.iters;
     const bool conc = p.concealed_weight > 0.0;
@@ -556,9 +571,22 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
     if (conc && p.pairs) return hipErrorInvalidValue;     // not combined
     const int opt = (p.prior_sigma > 0.0 ? 1 : 0) | (p.stop_ratio > 0.0 ? 2 : 0);
     if (opt && (conc || p.pairs || p.precision != RFSR_PREC_FP64)) return hipErrorInvalidValue;
-    if (p.precision == RFSR_PREC_FP32) {
+    if (p.precision == RFSR_PREC_FP32 || p.precision == RFSR_PREC_MIXED) {
         if (conc || p.pairs || opt) return hipErrorInvalidValue;
-        return launch_fsr_f32(js, total_blocks, p, tables, s);
+        const bool mixed = p.precision == RFSR_PREC_MIXED;
+        if (mixed && !rerun) return hipErrorInvalidValue;
+        MixedArgs mx;
+        mx.bound = (float)p.mixed_bound;
+        mx.count = rerun;
+        mx.list = rerun ? reinterpret_cast<int*>(rerun + kRerunList / 4) : nullptr;
+        mx.margins = p.block_margin;
+        hipError_t e = launch_fsr_f32(js, total_blocks, p, tables, s, mx, mixed ? 1 : (p.block_margin ? 2 : 0));
+        if (e != hipSuccess || !mixed) return e;
+        // the listed blocks in float64 (after the float32 pass, in stream order)
+        hipLaunchKernelGGL((fsr_block_kernel<RFSR_PREC_FP64, false, false, 0, true>), dim3(total_blocks), dim3(64),
+                           shmem, s, js, total_blocks, tables, p.iters, p.gamma, p.proj_weight, p.overwrite, 0.0,
+                           0, 0, 0.0, rerun, p.rerun_blocks);
+        return hipGetLastError();
     }
     auto kernel = fsr_block_kernel<RFSR_PREC_FP64, false, false>;
     if (opt == 1) kernel = fsr_block_kernel<RFSR_PREC_FP64, false, false, 1>;
@@ -578,7 +606,7 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
     }
     if (!conc) {
         hipLaunchKernelGGL(kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
-                           p.gamma, p.proj_weight, p.overwrite, 0.0, 0, 0, p.stop_ratio);
+                           p.gamma, p.proj_weight, p.overwrite, 0.0, 0, 0, p.stop_ratio, nullptr, nullptr);
         return hipGetLastError();
     }
     // wavefront: step t holds the blocks with 5 bi + bj = t of every frame
@@ -596,7 +624,7 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
         }
         if (grid == 0) continue;
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
-                           p.gamma, p.proj_weight, p.overwrite, p.concealed_weight, t, lo0, 0.0);
+                           p.gamma, p.proj_weight, p.overwrite, p.concealed_weight, t, lo0, 0.0, nullptr, nullptr);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

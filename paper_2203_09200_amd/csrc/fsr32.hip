@@ -24,6 +24,23 @@
 // Register layout of the iterations as in fsr.hip: lane (h, r) holds the bins
 // k = (j + 16 h, r), j = 0..15; W(k - b) for register j sits in table row
 // ((j - b1) mod 32) xor 16h, column (r - b2) mod 32.
+//
+// The mixed form (RFSR_PREC_MIXED) runs this kernel with a near-tie test and
+// recomputes the blocks that fail it with the float64 kernel.  The float32
+// residual differs from the float64 one by rounding that is dominated by the
+// block's FFT: of the order of u = 2^-24 times ||R^0||_2, the norm of the
+// block's initial weighted spectrum, in every bin, growing little over the
+// updates.  A pick can therefore differ from the float64 model's only where
+// the best and the next energy are that close.  So every iteration tests
+// whether any bin other than the pick (and, while the spectrum is Hermitian,
+// its conjugate partner, which ties exactly and gives the conjugate
+// trajectory) has an energy within 4 a u ||R^0||_2 |R_b| of the pick's, i.e.
+// |R_b| - |R_next| below about 2 a u ||R^0||_2; a block that does stops, puts
+// its index in a list and leaves its outputs to the float64 recomputation.
+// `a` (rfsr_fsr_params.mixed_bound) is set well above the rounding actually
+// seen at the flips (calibrated with the margin diagnostic below).  The
+// per-lane second-largest packed energy, which the test needs, is tracked
+// beside the maximum.
 #include "common.h"
 #include "fft.h"
 
@@ -39,6 +56,33 @@ __device__ __forceinline__ uint32_t pack_energy32(float e, uint32_t code) {
 }
 
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+// Three-operand unsigned max and median, written as single instructions: the
+// fold below reuses its running maxima, which keeps the backend from fusing
+// two-operand ones.
+__device__ __forceinline__ uint32_t vmax3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_max3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ uint32_t vmed3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Fold four packed energies into a lane's largest (m) and second largest
+// (m2): with m >= m2, the second largest of {m, m2, x, y} is
+// max(m2, med3(m, x, y)); two such steps, five instructions.
+__device__ __forceinline__ void fold4(uint32_t& m, uint32_t& m2, const uint32_t (&p)[4]) {
+    const uint32_t ma = vmax3(m, p[0], p[1]);
+    m2 = vmax3(m2, vmed3(m, p[0], p[1]), vmed3(ma, p[2], p[3]));
+    m = vmax3(ma, p[2], p[3]);
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
 
 constexpr int kPlane32 = 33;   // padded row length of a transpose plane
 
@@ -50,9 +94,15 @@ constexpr float kWScale = 128.0f;
 }  // namespace
 
 // Four waves per SIMD fit the LDS (8 KB table + twiddles + the list).
+// MODE 0: the plain float32 form.  MODE 1: the float32 pass of the mixed
+// form (near-tie test; a failing block is listed in `mx` and stops).  MODE 2:
+// the plain float32 form that also writes, per block, the smallest margin
+// (E_b - E_next) / (4 u ||R^0||_2 |R_b|) over its iterations (a diagnostic:
+// MODE 1 with bound a lists exactly the blocks whose margin is at most a).
+template <int MODE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void fsr_block_kernel_f32(
     Jobs<FrameJob> js, int total, const FsrTables* __restrict__ tab, int K, float gamma, float projw,
-    int overwrite) {
+    int overwrite, MixedArgs mx) {
     __shared__ __align__(16) float2 s_T[32 * 32];
     __shared__ float s_tw[64];
     extern __shared__ float4 list[];
@@ -147,6 +197,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         }
         __syncthreads();
     }
+    // near-tie scale 4 a u ||R^0||_2 (MODE 1; a = 1 for the MODE 2 margins)
+    float eps4 = 0.0f;
+    if constexpr (MODE != 0) {
+        float e = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) e = fmaf(Rr[j], Rr[j], fmaf(Ri[j], Ri[j], e));
+        eps4 = 4.0f * 0x1p-24f * sqrtf(wave_sum_f32(e)) * (MODE == 1 ? mx.bound : 1.0f);
+    }
     // The table holds g W with g = gamma / W0; the list keeps R_b.
     const float W0 = __shfl(Wr[0], 0);                   // kWScale * W(0)
     const float g = (W0 > 0.0f) ? gamma / W0 : 0.0f;      // table: gamma * W / W(0), the scale cancels
@@ -156,12 +214,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     __syncthreads();
 
     // 4. greedy iterations.
-    uint32_t lbe = 0u;   // packed local maximum (energies are >= 0)
+    uint32_t lbe = 0u, lbe2 = 0u;   // packed local maximum and second largest (energies are >= 0)
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-        lbe = umax(lbe, pack_energy32(fmaf(Rr[j], Rr[j], Ri[j] * Ri[j]), (uint32_t)(31 - 16 * h - j)));
+    for (int j = 0; j < 16; j += 4) {
+        uint32_t pk[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            pk[q] = pack_energy32(fmaf(Rr[j + q], Rr[j + q], Ri[j + q] * Ri[j + q]), (uint32_t)(31 - 16 * h - j - q));
+        if constexpr (MODE != 0) {
+            fold4(lbe, lbe2, pk);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lbe = umax(lbe, pk[q]);
+        }
+    }
     const uint8_t* Tb = smem;
     const uint32_t c8 = (uint32_t)c << 3, h12 = (uint32_t)h << 12;
+    bool herm = true;             // residual spectrum still Hermitian (only self-conjugate picks so far)
+    float mmin = __builtin_inff();
     for (int it = 0; it < K; ++it) {
         const uint32_t m = wave_max_u32(lbe);
         // lanes holding the maximal packed value share its row, so the first
@@ -170,6 +240,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         const int b1 = 31 - (int)(m & 31u);
         const int b2 = owner & 31;
         const int jb = b1 & 15;
+        if constexpr (MODE != 0) {
+            // the largest energy of every bin but the pick and (while the
+            // spectrum is Hermitian) its conjugate partner: the lane's second
+            // largest in those two lanes, its largest elsewhere
+            const float e1 = __uint_as_float(m);
+            const int p1 = (32 - b1) & 31, p2 = (32 - b2) & 31;
+            const int lane_p = ((p1 >> 4) << 5) | p2;
+            const bool excl = lane == owner || (herm && lane == lane_p);
+            const uint32_t other = excl ? lbe2 : lbe;
+            const float r1 = __builtin_amdgcn_sqrtf(e1);   // ~1 ulp: a threshold needs no more
+            if constexpr (MODE == 1) {
+                const uint32_t thr = __float_as_uint(fmaxf(fmaf(-eps4, r1, e1), 0.0f));
+                if (e1 > 0.0f && __ballot(other >= thr) != 0ull) {
+                    if (lane == 0) mx.list[atomicAdd(mx.count, 1u)] = gb;
+                    return;   // the float64 kernel recomputes this block
+                }
+            } else {
+                const float e2 = __uint_as_float(wave_max_u32(other));
+                if (e1 > 0.0f) mmin = fminf(mmin, (e1 - e2) / (eps4 * r1));
+            }
+            herm = herm && p1 == b1 && p2 == b2;
+        }
         const float dr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Rr[jb]), owner));
         const float di = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Ri[jb]), owner));
         if (lane == 0) list[it] = make_float4(__uint_as_float((uint32_t)(b1 * 32 + b2)), dr, di, 0.0f);
@@ -181,16 +273,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
             wt[j] = *reinterpret_cast<const float2*>(Tb + (S ^ L));
         }
         lbe = 0u;
+        lbe2 = 0u;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            float xr = fmaf(-dr, wt[j].x, Rr[j]);
-            xr = fmaf(di, wt[j].y, xr);
-            float xi = fmaf(-dr, wt[j].y, Ri[j]);
-            xi = fmaf(-di, wt[j].x, xi);
-            Rr[j] = xr;
-            Ri[j] = xi;
-            lbe = umax(lbe, pack_energy32(fmaf(xr, xr, xi * xi), (uint32_t)(31 - 16 * h - j)));
+        for (int j = 0; j < 16; j += 4) {
+            uint32_t pk[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float xr = fmaf(-dr, wt[j + q].x, Rr[j + q]);
+                xr = fmaf(di, wt[j + q].y, xr);
+                float xi = fmaf(-dr, wt[j + q].y, Ri[j + q]);
+                xi = fmaf(-di, wt[j + q].x, xi);
+                Rr[j + q] = xr;
+                Ri[j + q] = xi;
+                pk[q] = pack_energy32(fmaf(xr, xr, xi * xi), (uint32_t)(31 - 16 * h - j - q));
+            }
+            if constexpr (MODE != 0) {
+                fold4(lbe, lbe2, pk);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) lbe = umax(lbe, pk[q]);
+            }
         }
+    }
+    if constexpr (MODE == 2) {
+        if (lane == 0) mx.margins[gb] = mmin;
     }
     __syncthreads();
 
@@ -221,11 +327,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 }
 
 hipError_t launch_fsr_f32(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
-                          const FsrTables* tables, hipStream_t s) {
+                          const FsrTables* tables, hipStream_t s, const MixedArgs& mx, int mode) {
     if (total_blocks <= 0) return hipSuccess;
     const size_t shmem = sizeof(float4) * (size_t)p.iters;
-    hipLaunchKernelGGL(fsr_block_kernel_f32, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables,
-                       p.iters, (float)p.gamma, (float)p.proj_weight, p.overwrite);
+    auto kernel = fsr_block_kernel_f32<0>;
+    if (mode == 1) kernel = fsr_block_kernel_f32<1>;
+    else if (mode == 2) kernel = fsr_block_kernel_f32<2>;
+    hipLaunchKernelGGL(kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
+                       (float)p.gamma, (float)p.proj_weight, p.overwrite, mx);
     return hipGetLastError();
 }
 

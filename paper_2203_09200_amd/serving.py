@@ -495,7 +495,7 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--pool", type=int, default=8, help="distinct synthetic frames per size and mask kind")
-    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3", "fp32"], default="fp64",
+    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3", "fp32", "mixed"], default="fp64",
                     help="FSR arithmetic of the batched server (the plain loops are fp64 and fp32)")
     a = ap.parse_args(argv)
 

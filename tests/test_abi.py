@@ -95,8 +95,18 @@ def test_fsr_blocks_rejects_bad_arguments(R):
         c = p.c()
         assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == code, kw
     c = R.FSRParams().c()
-    c.precision = 4
+    c.precision = 5
     assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == -1
+    for bound in (0.0, -1.0, float("nan"), float("inf")):
+        c = R.FSRParams(precision="mixed").c()
+        c.mixed_bound = bound
+        assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == -1, bound
+    for kw in ({"pairs": True}, {"concealed_weight": 0.5}, {"prior_sigma": 0.8}, {"stop_ratio": 0.01}):
+        c = R.FSRParams(precision="mixed", **kw).c()
+        assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == -5, kw
+    # the mixed form needs its recomputation list in the workspace
+    n32 = lib.rfsr_workspace_bytes(1080, 1920, 0, None, ctypes.byref(R.FSRParams().c()))
+    assert n32 >= 17152 + 256 + 4 * 270 * 480
     c = R.FSRParams().c()
     c.overwrite = 7
     assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == -1

@@ -11,7 +11,8 @@ from _gpu import AMB_MAX, FSR_TOL, PSNR_TOL, compare_fsr, dev, host, need_gpu
 pytestmark = pytest.mark.gpu
 
 
-def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite="dfsr", me_opts=None):
+def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite="dfsr", me_opts=None,
+                        precision="fp64"):
     R = need_gpu()
     rng = np.random.default_rng(seed)
     frames, _ = synth.video_translate_edges(nref + 1, H, W, rng, max_step=3, n_edges=3)
@@ -29,7 +30,7 @@ def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite
     out, out_u8 = R.reconstruct_frame(dev(meas[t]), dev(masks[t]),
                                       [(dev(r), dev(mm), dev(b)) for r, mm, b in refs],
                                       R.MEParams(search=search, check=check, **me_opts),
-                                      R.FSRParams(iters=K, overwrite=overwrite))
+                                      R.FSRParams(iters=K, overwrite=overwrite, precision=precision))
     out, out_u8 = host(out), host(out_u8)
     worst, namb, nb = compare_fsr(out, ora["out"], ora["gaps"])
     print(f"frame {H}x{W} {check} {kind} nref={nref}: max {worst:.2e}, ambiguous {namb}/{nb}, "

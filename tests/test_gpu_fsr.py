@@ -127,3 +127,18 @@ def test_fsr_full_hd_sampled_blocks():
     print(f"1080p sample: max {d[~amb].max():.2e}, ambiguous {amb.sum()}/256")
     assert d[~amb].max() <= FSR_TOL
     assert amb.sum() <= AMB_MAX * 256
+
+
+def test_fsr_k1024_against_oracle():
+    """The longest supported run: the float64 kernel keeps each pick's R_b in
+    float32 in its synthesis list and writes a float32 output, an error of
+    about 2^-24 of the coefficients summed over K picks; at K = 1024 it stays
+    far inside the 1e-3 tolerance."""
+    R = need_gpu()
+    f, m, meas = frame(7, 32, 32)
+    vals = meas.astype(np.float64)
+    ora, gaps = O.fsr_frame(vals, m, K=1024)
+    out, _ = run_gpu(R, vals, m, K=1024)
+    worst, namb, nb = compare_fsr(out, ora, gaps)
+    print(f"K=1024 32x32: max {worst:.2e}, ambiguous {namb}/{nb}")
+    assert worst <= 1e-4 and namb <= AMB_MAX * nb
