@@ -68,17 +68,20 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def counters_from_profile():
-    """The committed PMC record of the FSR kernel (HBM bytes and VALU
-    wave-instructions per 1080p launch), or {} when the kernel's sources
-    changed since the counters were taken."""
-    from paper_2203_09200_amd.profiling import kernel_digest
-    path = os.path.join(ROOT, "profiles", "fsr_block_kernel_1080p_traffic.json")
+def counters_from_profile(precision="fp64"):
+    """The committed PMC record of one 1080p FSR launch in the given form (HBM
+    bytes and VALU wave-instructions; for mixed, the float32 pass and the
+    float64 recomputation together), or {} when there is none or the kernels'
+    sources changed since the counters were taken."""
+    from paper_2203_09200_amd.profiling import FORMS, kernel_digest
+    if precision not in FORMS:
+        return {}
+    path = os.path.join(ROOT, "profiles", FORMS[precision]["record"])
     if not os.path.exists(path):
         return {}
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_sha256") != kernel_digest():
+    if rec.get("kernel_sha256") != kernel_digest(precision):
         return {}
     return rec
 
@@ -201,19 +204,17 @@ def cpu_baseline(pool, cores, frames, masks, recons, me_o, fsr_o, rows_per_core=
                       f"strips per reference, FSR on block tiles; {dt:.1f} s"}
 
 
-def plain_fp32_form(a, seq_args, d_meas, d_mask, frames, ref_out, stream):
-    """The plain float32 form beside the float64 headline: the same recursion,
-    one frame at a time (no overlap of consecutive frames, no graphs), every
-    FSR step in float32; one untimed and one timed step of the sequence.
-    Reports throughput, PSNR and the distance of its outputs from the float64
-    form's."""
+def other_form(a, precision, pipelined, seq_args, d_meas, d_mask, frames, ref_out, stream, form):
+    """The same recursion with FSR in another arithmetic form, reported beside
+    the headline: one untimed and one timed step of the sequence.  Reports
+    throughput, PSNR and the distance of its outputs from the headline's."""
     import numpy as np
     import torch
     import paper_2203_09200_amd as R
     H, W, me, dev = seq_args
     F = len(d_meas)
-    fsr32 = R.FSRParams(iters=a.iters, precision="fp32")
-    seq = R.Sequence(H, W, me, fsr32, device=dev, pipelined=False)
+    prm = R.FSRParams(iters=a.iters, precision=precision)
+    seq = R.Sequence(H, W, me, prm, device=dev, pipelined=pipelined)
     outs = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(F)]
 
     def step():
@@ -233,12 +234,12 @@ def plain_fp32_form(a, seq_args, d_meas, d_mask, frames, ref_out, stream):
     d0 = np.abs(got[0].astype(np.float64) - ref_out[0]).reshape(H // 4, 4, W // 4, 4).max(axis=(1, 3))
     return {"value": round(F * H * W / dt / 1e6, 3), "unit": "HR Mpix/s", "ms_per_step": round(dt * 1e3, 3),
             "psnr_db": round(float(np.mean([psnr(frames[t], got[t]) for t in range(F)])), 3),
-            "max_abs_vs_f64": round(float(d.max()), 4),
-            "frac_px_over_1e-3_vs_f64": round(float((d > 1e-3).mean()), 5),
-            "frame0_blocks_within_1e-3_of_f64": round(float((d0 <= 1e-3).mean()), 5),
-            "frame0_max_abs_vs_f64": round(float(d0.max()), 4),
-            "form": "single stream, one frame at a time, FFT, table, residual and energies in float32 "
-                    "(precision fp32); one timed step"}
+            "max_abs_vs_headline": round(float(d.max()), 4),
+            "frac_px_over_1e-3_vs_headline": round(float((d > 1e-3).mean()), 5),
+            "frame0_blocks_within_1e-3_of_headline": round(float((d0 <= 1e-3).mean()), 5),
+            "frame0_max_abs_vs_headline": float(f"{d0.max():.4g}"),
+            "form": form + ("; pipelined as the headline" if pipelined else
+                            "; single stream, one frame at a time") + "; one timed step"}
 
 
 def run_multistream(a, dev):
@@ -365,12 +366,13 @@ def main(argv=None):
                     help="concealed weighting delta (> 0: raster-order blocks as a wavefront)")
     ap.add_argument("--pairs", action="store_true",
                     help="real-valued FSR (a conjugate pair per iteration; use about half the iterations)")
-    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3", "fp32", "mixed"], default="fp64",
-                    help="FSR arithmetic: float64 (default); block DFT as matrix-core GEMMs with split "
-                         "16-bit operands and float64 iterations; every step float32 (fp32); or float32 with "
-                         "a near-tie test and float64 for the blocks that fail it (mixed)")
-    ap.add_argument("--no-fp32-form", action="store_true",
-                    help="skip the plain float32 form reported beside the float64 result")
+    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3", "fp32", "mixed"], default="mixed",
+                    help="FSR arithmetic: float32 with a near-tie test and float64 for the blocks that fail it "
+                         "(mixed, default: the float64 model's result); float64 throughout (fp64); block DFT as "
+                         "matrix-core GEMMs with split 16-bit operands and float64 iterations; or every step "
+                         "float32 (fp32)")
+    ap.add_argument("--no-other-forms", "--no-fp32-form", action="store_true",
+                    help="skip the float32 (and, beside mixed, the float64) form reported beside the result")
     a = ap.parse_args(argv)
 
     if a.gpus != 1:
@@ -471,8 +473,8 @@ def run(a, pool, cores):
     nblk = (H // 4) * (W // 4)
     flops = fsr_flops_per_block(a.iters, a.pairs) * nblk
     achieved = flops / fsr_avg_s / 1e12
-    rec = counters_from_profile()
-    default_fsr = not (a.pairs or a.concealed or a.prior or a.stop or a.precision != "fp64") and \
+    rec = counters_from_profile(a.precision)
+    default_fsr = not (a.pairs or a.concealed or a.prior or a.stop) and a.precision in ("fp64", "mixed") and \
         a.iters == 100 and (H, W) == (1080, 1920)
     # the counters were taken on this kernel and workload only
     traffic = rec.get("bytes_per_launch") if default_fsr else None
@@ -484,8 +486,13 @@ def run(a, pool, cores):
                 "flops_per_launch": flops, "avg_launch_ms": round(fsr_avg_s * 1e3, 4)}
     if reruns is not None:
         n_re = int(reruns.item())
+        # frame 0 has no references: its FSR input is the measured frame, so the
+        # float64 form can run on the same input
+        o64, _ = R.fsr_blocks(d_meas[0].float(), d_mask[0], R.FSRParams(iters=a.iters))
+        d0 = np.abs(o64.cpu().numpy().astype(np.float64) - host_out[0]).reshape(H // 4, 4, W // 4, 4).max(axis=(1, 3))
         roofline["mixed"] = {"recomputed_in_f64": n_re, "blocks": nblk * F * a.steps,
                              "recomputed_frac": round(n_re / (nblk * F * a.steps), 5),
+                             "frame0_max_abs_vs_f64": float(f"{d0.max():.3g}"),
                              "note": "avg_launch_ms covers the float32 pass and the float64 recomputation"}
     if default_fsr and rec.get("valu_insts_per_dispatch"):
         # the same launch against the vector-ALU issue rate: one wave64 instruction per 4 cycles per SIMD
@@ -499,10 +506,13 @@ def run(a, pool, cores):
     if a.prior:
         roofline["note_prior"] = "the prior adds one multiply per bin and iteration, not counted"
 
-    fp32_form = None
-    if a.precision in ("fp64", "mixed") and not (a.pairs or a.concealed or a.prior or a.stop or a.no_fp32_form):
-        fp32_form = plain_fp32_form(a, seq_args=(H, W, me, dev), d_meas=d_meas, d_mask=d_mask, frames=frames,
-                                    ref_out=host_out, stream=stream)
+    fp32_form = fp64_form = None
+    if a.precision in ("fp64", "mixed") and not (a.pairs or a.concealed or a.prior or a.stop or a.no_other_forms):
+        legs = dict(seq_args=(H, W, me, dev), d_meas=d_meas, d_mask=d_mask, frames=frames, ref_out=host_out,
+                    stream=stream)
+        fp32_form = other_form(a, "fp32", False, form="every FSR step in float32 (precision fp32)", **legs)
+        if a.precision == "mixed":
+            fp64_form = other_form(a, "fp64", not a.no_pipeline, form="FSR in float64 (precision fp64)", **legs)
 
     cpu = None
     if pool is not None:
@@ -550,6 +560,7 @@ def run(a, pool, cores):
                                    "previous frame's FSR)" if not a.no_pipeline else "all references")},
         "psnr_db": round(q, 3),
         "roofline": roofline,
+        "fp64_form": fp64_form,
         "fp32_form": fp32_form,
         "cpu_baseline": cpu,
     }

@@ -272,7 +272,7 @@ rfsr_status fsr_blocks(const float* values, const uint8_t* cls, int32_t H, int32
 /* fsr_blocks without a workspace argument, for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation.  The call allocates nothing; its scratch (the FSR
- * tables, 17 KB, and for RFSR_PREC_MIXED the list of blocks to recompute,
+ * tables, 17 KB, and for RFSR_PREC_MIXED the lists of blocks to recompute,
  * 4 bytes per block + 256) lives in an array inside the library of
  * RFSR_NOALLOC_SCRATCH_BYTES per device (enough for the mixed form up to
  * about a million blocks, i.e. 16 megapixels), which every device that runs

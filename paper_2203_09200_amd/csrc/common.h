@@ -78,17 +78,25 @@ __device__ __forceinline__ int xcd_remap(int g, int n) {
 // ------------------------------------------------------------ workspaces --
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Scratch of the mixed-precision FSR: the number of blocks the float32 pass
-// listed for recomputation (first 256 bytes), then their flat indices.
-__host__ __device__ inline size_t rerun_bytes(size_t blocks) { return 256 + align256(4 * blocks); }
-constexpr size_t kRerunList = 256;
+// Scratch of the mixed-precision FSR: the blocks the float32 pass flags for
+// recomputation, one list per XCD (a launch of n blocks gives XCD x the
+// contiguous range of xcd_remap, at most rerun_cap(n) blocks).  First 256
+// bytes: the 8 list lengths; then list x at rerun_list(base, n, x).
+constexpr int kXcds = 8;
+__host__ __device__ inline int rerun_cap(int blocks) { return (blocks + kXcds - 1) / kXcds; }
+__host__ __device__ inline size_t rerun_bytes(size_t blocks) {
+    return 256 + align256(4 * (size_t)kXcds * (size_t)rerun_cap((int)blocks));
+}
+__device__ __forceinline__ int* rerun_list(unsigned* base, int blocks, int x) {
+    return reinterpret_cast<int*>(base + 64) + (size_t)x * rerun_cap(blocks);
+}
 
 // Arguments of the float32 kernel's mixed and diagnostic modes.
 struct MixedArgs {
-    float bound;          // near-tie bound a (units of 2^-24 ||R^0||_2)
-    unsigned* count;      // listed blocks
-    int* list;            // their flat block indices
-    float* margins;       // diagnostic: per-block smallest margin
+    float bound;                  // near-tie bound a (units of 2^-24 ||R^0||_2)
+    unsigned* rerun;              // rerun_bytes(total) of lists, lengths zeroed
+    unsigned long long* stats;    // nullable: += the number of blocks flagged
+    float* margins;               // diagnostic: per-block smallest margin
 };
 
 // Tables used by the FSR kernel (written by fsr_tables_kernel).
@@ -234,13 +242,13 @@ __host__ __device__ inline int frmc_groups(int H, int W) { return (H * W + kFrmc
 
 // --------------------------------------------------------------- launches --
 // Each returns hipSuccess or the launch error.
-// The FSR tables; also zeroes the mixed form's counter at `rerun` (nullable).
+// The FSR tables; also zeroes the mixed form's list lengths at `rerun` (nullable).
 hipError_t launch_fsr_tables(FsrTables* t, double rho, double prior_sigma, hipStream_t s,
                              unsigned* rerun = nullptr);
 // FSR over all `total_blocks` blocks of the frames in `js`.  With a
 // concealed weighting and a job table, `host_frames` is the host copy of the
 // table (frame sizes for the wavefront grid).  The mixed form needs `rerun`,
-// rerun_bytes(total_blocks) of scratch whose counter the tables launch zeroed.
+// rerun_bytes(total_blocks) of scratch whose list lengths the tables launch zeroed.
 hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
                       const FsrTables* tables, hipStream_t s, const FrameJob* host_frames = nullptr,
                       unsigned* rerun = nullptr);

@@ -246,7 +246,7 @@ __device__ __forceinline__ void dft_mfma(const double (&xs)[16], const double (&
 
 __global__ void fsr_tables_kernel(FsrTables* t, double rho, double sigma, unsigned* rerun) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && rerun) *rerun = 0u;   // the mixed form's list starts empty
+    if (i < kXcds && rerun) rerun[i] = 0u;   // the mixed form's lists start empty
     if (i < kSupport * kSupport) {
         const double dm = (i >> 5) - 15.5, dn = (i & 31) - 15.5;
         t->rho[i] = pow(rho, sqrt(dm * dm + dn * dn));
@@ -285,23 +285,33 @@ __global__ void fsr_tables_kernel(FsrTables* t, double rho, double sigma, unsign
 // pick's energies with the frequency prior of `tab`, bit 1 stops a block once
 // its pick's (weighted) energy falls below stop_ratio times its first.
 //
-// RERUN (the mixed form's float64 recomputation): workgroup i takes the
-// block rerun[kRerunList / 4 + i] of the list the float32 pass wrote, if i is
-// below the list's length rerun[0]; the grid covers every block, and the
-// workgroups beyond the length return at once.
+// RERUN (the mixed form's float64 recomputation): the float32 pass listed
+// the blocks it flagged per XCD, so the 8 lists concatenated run through the
+// frame's blocks roughly in order.  Workgroup g, dispatched to XCD
+// x = g mod 8, takes entry (g / 8) of the x-th eighth of that sequence: each
+// XCD recomputes an equal share of neighbouring blocks (their supports
+// overlap in its L2).  The grid covers every block; the workgroups beyond
+// the share return at once.
 template <int PREC, bool CONC, bool PAIRS, int OPT = 0, bool RERUN = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void fsr_block_kernel(
     Jobs<FrameJob> js, int total, const FsrTables* __restrict__ tab, int K, double gamma,
     double projw, int overwrite, double delta, int step, int bi0, double stop_ratio,
-    const unsigned* __restrict__ rerun, unsigned long long* rerun_stats) {
+    unsigned* __restrict__ rerun) {
     static_assert(OPT == 0 || (PREC == RFSR_PREC_FP64 && !CONC && !PAIRS), "options: plain loop only");
     static_assert(!RERUN || (PREC == RFSR_PREC_FP64 && !CONC && !PAIRS && OPT == 0), "rerun: plain loop");
     int gb_rerun = 0;
     if constexpr (RERUN) {
-        const unsigned n = *(const_ptr<unsigned>)(uintptr_t)rerun;
-        if (blockIdx.x >= n) return;
-        if (blockIdx.x == 0 && threadIdx.x == 0 && rerun_stats) atomicAdd(rerun_stats, (unsigned long long)n);
-        gb_rerun = (int)(*(const_ptr<unsigned>)(uintptr_t)(rerun + kRerunList / 4 + blockIdx.x));
+        const const_ptr<unsigned> len = (const_ptr<unsigned>)(uintptr_t)rerun;
+        int n = 0;
+#pragma unroll
+        for (int y = 0; y < kXcds; ++y) n += (int)len[y];
+        const int share = (n + kXcds - 1) / kXcds;
+        const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+        int e = x * share + i;   // entry of the concatenated lists
+        if (i >= share || e >= n) return;
+        int y = 0;
+        while (e >= (int)len[y]) e -= (int)len[y++];
+        gb_rerun = *(const_ptr<int>)(uintptr_t)(rerun_list(rerun, total, y) + e);
     }
     constexpr bool PRIOR = (OPT & 1) != 0, STOP = (OPT & 2) != 0;
     // W table (32 x 32 complex double); the transpose planes reuse it.  Static,
@@ -577,15 +587,17 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
         if (mixed && !rerun) return hipErrorInvalidValue;
         MixedArgs mx;
         mx.bound = (float)p.mixed_bound;
-        mx.count = rerun;
-        mx.list = rerun ? reinterpret_cast<int*>(rerun + kRerunList / 4) : nullptr;
+        mx.rerun = rerun;
+        mx.stats = p.rerun_blocks;
         mx.margins = p.block_margin;
         hipError_t e = launch_fsr_f32(js, total_blocks, p, tables, s, mx, mixed ? 1 : (p.block_margin ? 2 : 0));
         if (e != hipSuccess || !mixed) return e;
         // the listed blocks in float64 (after the float32 pass, in stream order)
-        hipLaunchKernelGGL((fsr_block_kernel<RFSR_PREC_FP64, false, false, 0, true>), dim3(total_blocks), dim3(64),
+        // every XCD gets as many workgroups as the largest share can need
+        hipLaunchKernelGGL((fsr_block_kernel<RFSR_PREC_FP64, false, false, 0, true>),
+                           dim3(kXcds * rerun_cap(total_blocks)), dim3(64),
                            shmem, s, js, total_blocks, tables, p.iters, p.gamma, p.proj_weight, p.overwrite, 0.0,
-                           0, 0, 0.0, rerun, p.rerun_blocks);
+                           0, 0, 0.0, rerun);
         return hipGetLastError();
     }
     auto kernel = fsr_block_kernel<RFSR_PREC_FP64, false, false>;
@@ -606,7 +618,7 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
     }
     if (!conc) {
         hipLaunchKernelGGL(kernel, dim3(total_blocks), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
-                           p.gamma, p.proj_weight, p.overwrite, 0.0, 0, 0, p.stop_ratio, nullptr, nullptr);
+                           p.gamma, p.proj_weight, p.overwrite, 0.0, 0, 0, p.stop_ratio, nullptr);
         return hipGetLastError();
     }
     // wavefront: step t holds the blocks with 5 bi + bj = t of every frame
@@ -624,7 +636,7 @@ hipError_t launch_fsr(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr
         }
         if (grid == 0) continue;
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(64), shmem, s, js, total_blocks, tables, p.iters,
-                           p.gamma, p.proj_weight, p.overwrite, p.concealed_weight, t, lo0, 0.0, nullptr, nullptr);
+                           p.gamma, p.proj_weight, p.overwrite, p.concealed_weight, t, lo0, 0.0, nullptr);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

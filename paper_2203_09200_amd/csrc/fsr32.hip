@@ -36,7 +36,8 @@
 // its conjugate partner, which ties exactly and gives the conjugate
 // trajectory) has an energy within 4 a u ||R^0||_2 |R_b| of the pick's, i.e.
 // |R_b| - |R_next| below about 2 a u ||R^0||_2; a block that does stops, puts
-// its index in a list and leaves its outputs to the float64 recomputation.
+// its index in its XCD's list and leaves its outputs to the float64
+// recomputation.
 // `a` (rfsr_fsr_params.mixed_bound) is set well above the rounding actually
 // seen at the flips (calibrated with the margin diagnostic below).  The
 // per-lane second-largest packed energy, which the test needs, is tracked
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     int overwrite, MixedArgs mx) {
     __shared__ __align__(16) float2 s_T[32 * 32];
     __shared__ float s_tw[64];
-    extern __shared__ float4 list[];
+    extern __shared__ float list[];   // K entries (bin, Re R_b, Im R_b)
     uint8_t* smem = reinterpret_cast<uint8_t*>(s_T);
 
     const int lane = threadIdx.x;
@@ -253,8 +254,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
             if constexpr (MODE == 1) {
                 const uint32_t thr = __float_as_uint(fmaxf(fmaf(-eps4, r1, e1), 0.0f));
                 if (e1 > 0.0f && __ballot(other >= thr) != 0ull) {
-                    if (lane == 0) mx.list[atomicAdd(mx.count, 1u)] = gb;
-                    return;   // the float64 kernel recomputes this block
+                    if (lane == 0) {   // the float64 kernel recomputes this block
+                        const int x = blockIdx.x % kXcds;
+                        rerun_list(mx.rerun, total, x)[atomicAdd(mx.rerun + x, 1u)] = gb;
+                        if (mx.stats) atomicAdd(mx.stats, 1ull);
+                    }
+                    return;
                 }
             } else {
                 const float e2 = __uint_as_float(wave_max_u32(other));
@@ -264,7 +269,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         }
         const float dr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Rr[jb]), owner));
         const float di = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Ri[jb]), owner));
-        if (lane == 0) list[it] = make_float4(__uint_as_float((uint32_t)(b1 * 32 + b2)), dr, di, 0.0f);
+        if (lane == 0) {
+            list[3 * it] = __uint_as_float((uint32_t)(b1 * 32 + b2));
+            list[3 * it + 1] = dr;
+            list[3 * it + 2] = di;
+        }
         const uint32_t L = ((c8 - (uint32_t)b2 * 8u) & 0xF8u) | h12;   // per-lane column part
         float2 wt[16];
 #pragma unroll
@@ -305,11 +314,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     const int pm = 14 + (p >> 2), pn = 14 + (p & 3);
     float gr = 0.0f;
     for (int it = q; it < K; it += 4) {
-        const float4 e = list[it];
-        const uint32_t bf = __float_as_uint(e.x);
+        const uint32_t bf = __float_as_uint(list[3 * it]);
         const int t = ((int)(bf >> 5) * pm + (int)(bf & 31) * pn) & 31;
-        gr = fmaf(e.y, s_tw[2 * t], gr);       // Re(R_b exp(+2 pi i t / 32))
-        gr = fmaf(e.z, s_tw[2 * t + 1], gr);
+        gr = fmaf(list[3 * it + 1], s_tw[2 * t], gr);       // Re(R_b exp(+2 pi i t / 32))
+        gr = fmaf(list[3 * it + 2], s_tw[2 * t + 1], gr);
     }
     gr += __shfl_xor(gr, 16);
     gr += __shfl_xor(gr, 32);
@@ -329,7 +337,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 hipError_t launch_fsr_f32(const Jobs<FrameJob>& js, int total_blocks, const rfsr_fsr_params& p,
                           const FsrTables* tables, hipStream_t s, const MixedArgs& mx, int mode) {
     if (total_blocks <= 0) return hipSuccess;
-    const size_t shmem = sizeof(float4) * (size_t)p.iters;
+    // 12 bytes per list entry: with the 8.25 KB of static tables a workgroup
+    // takes 19 of the CU's 320 LDS granules of 512 bytes at K = 100, so
+    // sixteen (four waves per SIMD) leave room for a workgroup of another
+    // kernel on the CU (the next frame's motion path on a side stream)
+    const size_t shmem = 3 * sizeof(float) * (size_t)p.iters;
     auto kernel = fsr_block_kernel_f32<0>;
     if (mode == 1) kernel = fsr_block_kernel_f32<1>;
     else if (mode == 2) kernel = fsr_block_kernel_f32<2>;

@@ -9,12 +9,14 @@
 size once with torch (reads and writes exactly `mib` MiB), so FETCH_SIZE and
 WRITE_SIZE of the same run calibrate the counters' units.
 
-`record` writes profiles/fsr_block_kernel_1080p_traffic.json from the
-per-dispatch counter values read off the rocprofv3 CSVs, keyed by the
-SHA-256 of the kernel's sources (KERNEL_SOURCES), so that bench.py reports
-`traffic` only while the kernel is unchanged.  With --sq-csv (a run that collected SQ_INSTS_VALU)
-it also records the VALU wave-instructions per dispatch, from which bench.py
-reports the kernel's position against the vector-ALU issue rate.
+`record [--precision fp64|mixed]` writes the form's record under profiles/
+(FORMS) from the per-dispatch counter values read off the rocprofv3 CSVs,
+keyed by the SHA-256 of the kernels' sources, so that bench.py reports
+`traffic` only while the kernels are unchanged.  A mixed launch is two
+dispatches (the float32 pass and the float64 recomputation of the listed
+blocks); its record adds their per-dispatch averages.  With --sq-csv (a run that
+collected SQ_INSTS_VALU) it also records the VALU wave-instructions per launch,
+from which bench.py reports the position against the vector-ALU issue rate.
 """
 from __future__ import annotations
 
@@ -28,14 +30,22 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
-# sources that compile into fsr_block_kernel
-KERNEL_SOURCES = ("fsr.hip", "fft.h", "common.h")
+# per FSR form: the sources its kernels compile from, the kernel-name prefixes
+# of its dispatches, and the record file under profiles/
+FORMS = {
+    "fp64": {"sources": ("fsr.hip", "fft.h", "common.h"), "kernels": ("fsr_block_kernel<",),
+             "record": "fsr_block_kernel_1080p_traffic.json"},
+    "mixed": {"sources": ("fsr32.hip", "fsr.hip", "fft.h", "common.h"),
+              "kernels": ("fsr_block_kernel_f32<", "fsr_block_kernel<"),
+              "record": "fsr_mixed_1080p_traffic.json"},
+}
+KERNEL_SOURCES = FORMS["fp64"]["sources"]
 
 
-def kernel_digest() -> str:
-    """SHA-256 over the FSR kernel's sources, in a fixed order."""
+def kernel_digest(precision: str = "fp64") -> str:
+    """SHA-256 over the sources of the form's FSR kernels, in a fixed order."""
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in FORMS[precision]["sources"]:
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -85,28 +95,38 @@ def _counter_per_dispatch(csv_path: str, kernel_substr: str, counter: str):
     return vals
 
 
-def record(fsr_fetch_csv, fsr_write_csv, copy_fetch_csv, copy_write_csv, copy_mib, copy_kernel, sq_csv=None):
-    ff = _counter_per_dispatch(fsr_fetch_csv, "fsr_block_kernel<", "FETCH_SIZE")
-    fw = _counter_per_dispatch(fsr_write_csv, "fsr_block_kernel<", "WRITE_SIZE")
+def _per_launch(csv_path, kernels, counter):
+    """Sum over the form's kernels of the counter's per-dispatch average."""
+    total = 0.0
+    for k in kernels:
+        v = _counter_per_dispatch(csv_path, k, counter)
+        if not v:
+            raise SystemExit(f"no {counter} rows for {k} in {csv_path}")
+        total += sum(v) / len(v)
+    return total
+
+
+def record(fsr_fetch_csv, fsr_write_csv, copy_fetch_csv, copy_write_csv, copy_mib, copy_kernel, sq_csv=None,
+           precision="fp64"):
+    form = FORMS[precision]
+    ff = _per_launch(fsr_fetch_csv, form["kernels"], "FETCH_SIZE")
+    fw = _per_launch(fsr_write_csv, form["kernels"], "WRITE_SIZE")
     cf = _counter_per_dispatch(copy_fetch_csv, copy_kernel, "FETCH_SIZE")
     cw = _counter_per_dispatch(copy_write_csv, copy_kernel, "WRITE_SIZE")
     nbytes = copy_mib << 20
     # counters read in KiB; the copy of known size fixes the scale of each
     s_fetch = nbytes / max(cf) if cf else None
     s_write = nbytes / max(cw) if cw else None
-    fetch_b = sum(ff) / len(ff) * s_fetch
-    write_b = sum(fw) / len(fw) * s_write
-    rec = {"kernel": "fsr_block_kernel", "workload": "1920x1080 frame, dynamic mask, K=100",
-           "kernel_sources": list(KERNEL_SOURCES), "kernel_sha256": kernel_digest(), "fetch_kib_per_dispatch": sum(ff) / len(ff),
-           "write_kib_per_dispatch": sum(fw) / len(fw), "copy_mib": copy_mib,
+    rec = {"kernel": " + ".join(k.rstrip("<") for k in form["kernels"]), "precision": precision,
+           "workload": "1920x1080 frame, dynamic mask, K=100",
+           "kernel_sources": list(form["sources"]), "kernel_sha256": kernel_digest(precision),
+           "fetch_kib_per_dispatch": ff, "write_kib_per_dispatch": fw, "copy_mib": copy_mib,
            "copy_fetch_kib": max(cf), "copy_write_kib": max(cw),
            "fetch_scale_bytes_per_unit": s_fetch, "write_scale_bytes_per_unit": s_write,
-           "bytes_per_launch": fetch_b + write_b}
+           "bytes_per_launch": ff * s_fetch + fw * s_write}
     if sq_csv:
-        vi = _counter_per_dispatch(sq_csv, "fsr_block_kernel<", "SQ_INSTS_VALU")
-        if vi:
-            rec["valu_insts_per_dispatch"] = sum(vi) / len(vi)
-    out = os.path.join(ROOT, "profiles", "fsr_block_kernel_1080p_traffic.json")
+        rec["valu_insts_per_dispatch"] = _per_launch(sq_csv, form["kernels"], "SQ_INSTS_VALU")
+    out = os.path.join(ROOT, "profiles", form["record"])
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
@@ -131,6 +151,7 @@ def main(argv=None):
     a3.add_argument("--copy-mib", type=int, default=1024)
     a3.add_argument("--copy-kernel", default="copyBuffer")
     a3.add_argument("--sq-csv", default=None, help="counter CSV of a run with SQ_INSTS_VALU")
+    a3.add_argument("--precision", choices=sorted(FORMS), default="fp64")
     a = ap.parse_args(argv)
     if a.cmd == "fsr":
         run_fsr(a.reps, a.delta, a.precision, a.iters)
@@ -138,7 +159,7 @@ def main(argv=None):
         run_copy(a.mib)
     else:
         record(a.fsr_fetch_csv, a.fsr_write_csv, a.copy_fetch_csv, a.copy_write_csv, a.copy_mib,
-               a.copy_kernel, a.sq_csv)
+               a.copy_kernel, a.sq_csv, a.precision)
     return 0
 
 

@@ -104,9 +104,9 @@ def test_fsr_blocks_rejects_bad_arguments(R):
     for kw in ({"pairs": True}, {"concealed_weight": 0.5}, {"prior_sigma": 0.8}, {"stop_ratio": 0.01}):
         c = R.FSRParams(precision="mixed", **kw).c()
         assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == -5, kw
-    # the mixed form needs its recomputation list in the workspace
+    # the mixed form's recomputation lists (4 bytes per block) are part of the workspace
     n32 = lib.rfsr_workspace_bytes(1080, 1920, 0, None, ctypes.byref(R.FSRParams().c()))
-    assert n32 >= 17152 + 256 + 4 * 270 * 480
+    assert n32 >= 16896 + 256 + 4 * 270 * 480
     c = R.FSRParams().c()
     c.overwrite = 7
     assert lib.fsr_blocks(fake, fake, 8, 8, 8, ctypes.byref(c), fake, None, fake, 1 << 20, None) == -1
@@ -131,6 +131,13 @@ def test_fsr_blocks_noalloc_rejects_bad_arguments(R):
     assert lib.fsr_blocks_noalloc(fake, fake, 8, 8, 8, None, fake, None, None) == -1
     for H, W, pitch in ((6, 8, 8), (8, 10, 10), (8, 8, 4), (20000, 8, 8)):
         assert lib.fsr_blocks_noalloc(fake, fake, H, W, pitch, ctypes.byref(c), fake, None, None) == -2
+    # mixed frames whose recomputation lists (4 bytes per block + 256) do not fit
+    # next to the 16,896-byte tables in the 4 MB array: RFSR_EWORKSPACE before
+    # any device access
+    c = R.FSRParams(precision="mixed").c()
+    for H, W in ((16384, 16384), (8192, 8192), (4096, 4096), (4096, 4088)):
+        assert 16896 + 256 + 4 * (H // 4) * (W // 4) > 4194304
+        assert lib.fsr_blocks_noalloc(fake, fake, H, W, W, ctypes.byref(c), fake, None, None) == -3, (H, W)
 
 
 def test_me_params_options_validation(R):

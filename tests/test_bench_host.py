@@ -60,18 +60,21 @@ def test_counter_record_is_used_only_for_the_measured_sources(tmp_path, monkeypa
     assert bench.counters_from_profile()["bytes_per_launch"] == 123.0
 
 
-def test_kernel_digest_covers_every_source(tmp_path, monkeypatch):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_kernel_digest_covers_every_source(tmp_path, monkeypatch, precision):
     csrc = tmp_path / "csrc"
     csrc.mkdir()
-    for name in profiling.KERNEL_SOURCES:
+    names = profiling.FORMS[precision]["sources"]
+    for name in names:
         (csrc / name).write_text(name)
     monkeypatch.setattr(profiling, "HERE", str(tmp_path))
-    d0 = profiling.kernel_digest()
-    for name in profiling.KERNEL_SOURCES:
+    d0 = profiling.kernel_digest(precision)
+    for name in names:
         (csrc / name).write_text(name + " changed")
-        assert profiling.kernel_digest() != d0, name
+        assert profiling.kernel_digest(precision) != d0, name
         (csrc / name).write_text(name)
-    assert profiling.kernel_digest() == d0
+    assert profiling.kernel_digest(precision) == d0
+    assert "fsr32.hip" in profiling.FORMS["mixed"]["sources"]   # the float32 pass is part of a mixed launch
 
 
 def test_traffic_record_scales_counters_by_the_copy(tmp_path, monkeypatch):
@@ -133,3 +136,32 @@ def test_banded_oracle_equals_whole_frame_oracle():
 
 def test_cpu_cores_is_one_gpu_share():
     assert 1 <= bench.cpu_cores() <= 16
+
+
+def test_mixed_record_adds_the_float32_pass_and_the_recomputation(tmp_path, monkeypatch):
+    """A mixed launch is two dispatches; its record adds their per-dispatch
+    averages, and the float64 kernel's name does not also match the float32
+    pass's."""
+    def csv_file(name, rows):
+        p = tmp_path / name
+        lines = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+        lines += [f'{d},"{k}",{c},{v}' for d, k, c, v in rows]
+        p.write_text("\n".join(lines) + "\n")
+        return str(p)
+    k32 = "void rfsr::fsr_block_kernel_f32<1>(args)"
+    k64 = "void rfsr::fsr_block_kernel<0, false, false, 0, true>(args)"
+    ff = csv_file("ff.csv", [(1, k32, "FETCH_SIZE", 100.0), (2, k64, "FETCH_SIZE", 10.0),
+                             (3, k32, "FETCH_SIZE", 300.0), (4, k64, "FETCH_SIZE", 30.0)])
+    fw = csv_file("fw.csv", [(1, k32, "WRITE_SIZE", 50.0), (2, k64, "WRITE_SIZE", 5.0)])
+    cf = csv_file("cf.csv", [(1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 1024.0)])
+    cw = csv_file("cw.csv", [(1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0)])
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(profiling, "ROOT", str(tmp_path))
+    profiling.record(ff, fw, cf, cw, 1, "copyBuffer", precision="mixed")
+    rec = json.loads((tmp_path / "profiles" / "fsr_mixed_1080p_traffic.json").read_text())
+    assert rec["fetch_kib_per_dispatch"] == 200.0 + 20.0 and rec["write_kib_per_dispatch"] == 55.0
+    assert rec["bytes_per_launch"] == (220.0 + 55.0) * 1024.0
+    assert rec["kernel_sha256"] == profiling.kernel_digest("mixed")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counters_from_profile("mixed")["bytes_per_launch"] == rec["bytes_per_launch"]
+    assert bench.counters_from_profile("fp64") == {} and bench.counters_from_profile("fp32") == {}
