@@ -12,6 +12,10 @@ TAU_FP64 = 1e-10
 TAU_FP32 = 1e-5
 AMB_MAX = 0.005      # share of blocks that may be tie-ambiguous under TAU_FP64
 FSR_TOL = 1e-3       # max-abs tolerance of FSR outputs on the 0..255 scale
+# The FSR forms held to the float64 model (tolerance FSR_TOL under TAU_FP64):
+# float64 throughout, and float32 with float64 for the blocks whose picks
+# float32 cannot vouch for.
+FLOAT64_FORMS = ("fp64", "mixed")
 PSNR_TOL = 0.01      # dB
 
 

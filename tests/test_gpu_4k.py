@@ -8,7 +8,7 @@ import torch
 
 import oracle as O
 import synth
-from _gpu import AMB_MAX, FSR_TOL, TAU_FP64, check_support_fields, dev, host, need_gpu
+from _gpu import AMB_MAX, FLOAT64_FORMS, FSR_TOL, TAU_FP64, check_support_fields, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -22,11 +22,12 @@ def seq():
 
 
 @pytest.mark.parametrize("K", [100, 300])
-def test_4k_fsr_sampled_blocks(seq, K):
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_4k_fsr_sampled_blocks(seq, K, precision):
     R = need_gpu()
     f, m, meas = seq
     vals = meas[0].astype(np.float64)
-    out, _ = R.fsr_blocks(dev(vals, torch.float32), dev(m[0]), R.FSRParams(iters=K))
+    out, _ = R.fsr_blocks(dev(vals, torch.float32), dev(m[0]), R.FSRParams(iters=K, precision=precision))
     out = host(out)
     rng = np.random.default_rng(K)
     nb = 192
@@ -36,12 +37,13 @@ def test_4k_fsr_sampled_blocks(seq, K):
     got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
     d = np.abs(got - ora).max(axis=(1, 2))
     amb = gaps < TAU_FP64
-    print(f"4K K={K}: max {d[~amb].max():.2e}, ambiguous {amb.sum()}/{nb}")
+    print(f"4K {precision} K={K}: max {d[~amb].max():.2e}, ambiguous {amb.sum()}/{nb}")
     assert d[~amb].max() <= FSR_TOL
     assert amb.sum() <= AMB_MAX * nb
 
 
-def test_4k_recursive_frame_sampled(seq):
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_4k_recursive_frame_sampled(seq, precision):
     """Frame 3 with three references (teacher-forced: ground-truth frames as
     reconstructions), NNC -> FRMC: forward vectors and costs at sampled
     pixels bit-exact, NNC -> FRMC decisions at the sampled pixels bit-exact,
@@ -53,7 +55,7 @@ def test_4k_recursive_frame_sampled(seq):
     refs = [(f[3 - k], meas[3 - k], m[3 - k]) for k in (1, 2, 3)]
     me_g = R.MEParams(search=9, check="nnc_frmc")
     out, out_u8 = R.reconstruct_frame(dev(meas[3]), dev(m[3]), [(dev(a), dev(b), dev(c)) for a, b, c in refs],
-                                      me_g, R.FSRParams(iters=100))
+                                      me_g, R.FSRParams(iters=100, precision=precision))
     out = host(out)
     cur, mask = meas[3], m[3]
     rng = np.random.default_rng(11)
@@ -80,7 +82,7 @@ def test_4k_recursive_frame_sampled(seq):
     got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
     d = np.abs(got - ora).max(axis=(1, 2))
     amb = gaps < TAU_FP64
-    print(f"4K frame 3: FSR max {d[~amb].max():.2e} over {(~amb).sum()} blocks, "
+    print(f"4K frame 3 ({precision}): FSR max {d[~amb].max():.2e} over {(~amb).sum()} blocks, "
           f"projected {(cls == 2).mean():.3f} of pixels")
     assert d[~amb].max() <= FSR_TOL
     assert amb.sum() <= AMB_MAX * len(blocks)

@@ -10,13 +10,15 @@ import pytest
 
 import oracle as O
 import synth
-from _gpu import FSR_TOL, PSNR_TOL, AMB_MAX, TAU_FP64, check_support_fields, compare_fsr, dev, host, need_gpu
+from _gpu import (AMB_MAX, FLOAT64_FORMS, FSR_TOL, PSNR_TOL, TAU_FP64, check_support_fields, compare_fsr, dev, host,
+                  need_gpu)
 
 pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("check", ["rme", "rmc"])
-def test_cpu_sized_recursion(check):
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_cpu_sized_recursion(check, precision):
     """128x128, 4 frames, fixed mask, R = 8: every frame's motion fields and
     decisions bit-exact (both sides fed the same uint8 reconstructions), FSR
     within tolerance, and the free-running PSNR of each frame within 0.01 dB."""
@@ -24,7 +26,7 @@ def test_cpu_sized_recursion(check):
     frames, masks = synth.workload_c1()
     meas = synth.measured(frames, masks)
     me_o, fsr_o = O.MEParams(search=8, check=check), O.FSRParams(iters=100)
-    me_g, fsr_g = R.MEParams(search=8, check=check), R.FSRParams(iters=100)
+    me_g, fsr_g = R.MEParams(search=8, check=check), R.FSRParams(iters=100, precision=precision)
     ora = O.reconstruct_sequence(meas, masks, me_o, fsr_o, track_gaps=True)
     seq = R.Sequence(128, 128, me_g, fsr_g)
     for t in range(4):
@@ -41,18 +43,19 @@ def test_cpu_sized_recursion(check):
             assert np.array_equal(host(mv)[0], f["alpha"]) and np.array_equal(host(mv)[1], f["beta"])
             assert np.array_equal(host(acc).astype(bool), f["accept"]), (t, k)
         worst, namb, nb = compare_fsr(out, tf["out"], tf["gaps"])
-        print(f"{check} t={t}: max {worst:.2e}, ambiguous {namb}/{nb}, "
+        print(f"{check} {precision} t={t}: max {worst:.2e}, ambiguous {namb}/{nb}, "
               f"PSNR gpu {O.psnr(frames[t], out):.4f} oracle {O.psnr(frames[t], ora[t]['out']):.4f}")
         assert worst <= FSR_TOL
         assert abs(O.psnr(frames[t], out) - O.psnr(frames[t], ora[t]["out"])) <= PSNR_TOL
 
 
-def test_1080p_recursive_frame_sampled():
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_1080p_recursive_frame_sampled(precision):
     R = need_gpu()
     H, W = 1080, 1920
     frames, masks = synth.workload_c2(n=4, h=H, w=W)
     meas = synth.measured(frames, masks)
-    me_g, fsr_g = R.MEParams(search=9, check="nnc_frmc"), R.FSRParams(iters=100)
+    me_g, fsr_g = R.MEParams(search=9, check="nnc_frmc"), R.FSRParams(iters=100, precision=precision)
     seq = R.Sequence(H, W, me_g, fsr_g, pipelined=True)   # as bench.py runs it
     for t in range(3):
         seq.push(dev(meas[t]), dev(masks[t]))
@@ -95,7 +98,7 @@ def test_1080p_recursive_frame_sampled():
     got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
     d = np.abs(got - ora).max(axis=(1, 2))
     amb = gaps < TAU_FP64
-    print(f"1080p frame 3: FSR max {d[~amb].max():.2e} over {(~amb).sum()} blocks "
+    print(f"1080p frame 3 ({precision}): FSR max {d[~amb].max():.2e} over {(~amb).sum()} blocks "
           f"(8 end to end: max {d[:8].max():.2e}), projected {(cls == 2).mean():.3f} of pixels")
     assert d[~amb].max() <= FSR_TOL
     assert amb.sum() <= AMB_MAX * len(blocks)

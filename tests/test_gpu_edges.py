@@ -7,19 +7,20 @@ import torch
 
 import oracle as O
 import synth
-from _gpu import FSR_TOL, TAU_FP64, dev, host, need_gpu
+from _gpu import FLOAT64_FORMS, FSR_TOL, TAU_FP64, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("H,W", [(16, 16384), (16384, 12), (4, 4), (4, 64), (64, 4)])
-def test_fsr_extreme_shapes_sampled(H, W):
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_fsr_extreme_shapes_sampled(H, W, precision):
     R = need_gpu()
     rng = np.random.default_rng(H + W)
     f = np.clip(128 + 40 * synth.bandlimited_noise(H, W, 2.0, rng), 0, 255).astype(np.uint8)
     m = synth.fixed_mask(H, W, rng)
     vals = (f * m).astype(np.float64)
-    out, _ = R.fsr_blocks(dev(vals, torch.float32), dev(m), R.FSRParams(iters=40))
+    out, _ = R.fsr_blocks(dev(vals, torch.float32), dev(m), R.FSRParams(iters=40, precision=precision))
     out = host(out)
     nbh, nbw = H // 4, W // 4
     idx = rng.choice(nbh * nbw, size=min(64, nbh * nbw), replace=False)
@@ -32,7 +33,7 @@ def test_fsr_extreme_shapes_sampled(H, W):
     amb = gaps < TAU_FP64
     assert np.isfinite(out).all()
     if (~amb).any():      # a frame of one block may hold only a near tie
-        print(f"{H}x{W}: max {d[~amb].max():.2e} over {(~amb).sum()} blocks")
+        print(f"{H}x{W} {precision}: max {d[~amb].max():.2e} over {(~amb).sum()} blocks")
         assert d[~amb].max() <= FSR_TOL
 
 

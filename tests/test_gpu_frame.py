@@ -6,7 +6,7 @@ import torch
 
 import oracle as O
 import synth
-from _gpu import AMB_MAX, FSR_TOL, PSNR_TOL, compare_fsr, dev, host, need_gpu
+from _gpu import AMB_MAX, FLOAT64_FORMS, FSR_TOL, PSNR_TOL, compare_fsr, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +33,7 @@ def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite
                                       R.FSRParams(iters=K, overwrite=overwrite, precision=precision))
     out, out_u8 = host(out), host(out_u8)
     worst, namb, nb = compare_fsr(out, ora["out"], ora["gaps"])
-    print(f"frame {H}x{W} {check} {kind} nref={nref}: max {worst:.2e}, ambiguous {namb}/{nb}, "
+    print(f"frame {precision} {H}x{W} {check} {kind} nref={nref}: max {worst:.2e}, ambiguous {namb}/{nb}, "
           f"projected {(ora['cls'] == 2).mean():.3f}")
     assert worst <= FSR_TOL
     assert namb <= AMB_MAX * nb
@@ -45,12 +45,14 @@ def teacher_forced_case(H, W, check, kind, nref, seed, K=60, search=8, overwrite
 @pytest.mark.parametrize("check,kind,nref", [("nnc_frmc", "dynamic", 3), ("rme", "fixed", 2),
                                              ("rmc", "dynamic", 1), ("none", "dynamic", 3),
                                              ("frmc", "fixed", 3), ("nnc", "dynamic", 2)])
-def test_frame_teacher_forced(check, kind, nref):
-    teacher_forced_case(64, 80, check, kind, nref, seed=10 + nref)
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_frame_teacher_forced(check, kind, nref, precision):
+    teacher_forced_case(64, 80, check, kind, nref, seed=10 + nref, precision=precision)
 
 
-def test_frame_rfsr_overwrite():
-    teacher_forced_case(64, 64, "nnc_frmc", "dynamic", 3, seed=3, overwrite="rfsr")
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_frame_rfsr_overwrite(precision):
+    teacher_forced_case(64, 64, "nnc_frmc", "dynamic", 3, seed=3, overwrite="rfsr", precision=precision)
 
 
 def test_frame_no_reference_is_single_frame_fsr():
@@ -130,7 +132,8 @@ def test_frame_ignores_unmeasured_values(check):
 
 
 @pytest.mark.parametrize("check", ["nnc_frmc", "rmc", "rme"])
-def test_frame_split_equals_whole(check):
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_frame_split_equals_whole(check, precision):
     """rfsr_frame_motion(first) + rfsr_frame_finish(first) on one workspace
     give bit-identical outputs to rfsr_reconstruct_frame for every split
     point first = 0..3 (ragged 44x60 frame, three references)."""
@@ -142,7 +145,7 @@ def test_frame_split_equals_whole(check):
     meas = synth.measured(frames, masks)
     refs = [(dev(frames[2 - k]), dev(meas[2 - k]), dev(masks[2 - k])) for k in range(3)]
     cur, mask = dev(meas[3]), dev(masks[3])
-    me, fsr = R.MEParams(search=6, check=check), R.FSRParams(iters=30)
+    me, fsr = R.MEParams(search=6, check=check), R.FSRParams(iters=30, precision=precision)
     o, u = R.reconstruct_frame(cur, mask, refs, me, fsr)
     whole = (host(o), host(u))
     nbytes = R.workspace_bytes(H, W, 3, me, fsr)
@@ -158,7 +161,8 @@ def test_frame_split_equals_whole(check):
                                               (64, 80, 6, "rmc", 3), (64, 80, 6, "frmc", 3),
                                               (64, 80, 6, "none", 3), (64, 80, 6, "nnc_frmc", 2),
                                               (64, 80, 5, "nnc_frmc", 1), (1080, 1920, 5, "nnc_frmc", 3)])
-def test_pipelined_sequence_equals_plain(H, W, T, check, nref):
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_pipelined_sequence_equals_plain(H, W, T, check, nref, precision):
     """The pipelined recursion (early motion path of the lag >= 2 references
     on a side stream, overlapping the previous frame's FSR) reproduces the
     plain recursion bit for bit, frame by frame."""
@@ -168,7 +172,7 @@ def test_pipelined_sequence_equals_plain(H, W, T, check, nref):
     d_meas = [dev(x) for x in meas]
     d_mask = [dev(x) for x in masks]
     torch.cuda.synchronize()
-    me, fsr = R.MEParams(search=9, check=check), R.FSRParams(iters=100)
+    me, fsr = R.MEParams(search=9, check=check), R.FSRParams(iters=100, precision=precision)
     res = []
     for pipelined in (False, True):
         seq = R.Sequence(H, W, me, fsr, nref=nref, pipelined=pipelined)

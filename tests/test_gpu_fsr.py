@@ -8,15 +8,15 @@ import torch
 
 import oracle as O
 import synth
-from _gpu import AMB_MAX, FSR_TOL, TAU_FP64, PSNR_TOL, compare_fsr, dev, host, need_gpu
+from _gpu import AMB_MAX, FLOAT64_FORMS, FSR_TOL, TAU_FP64, PSNR_TOL, compare_fsr, dev, host, need_gpu
 
 pytestmark = pytest.mark.gpu
 
 
-def run_gpu(R, values, cls, K=100, overwrite="dfsr", rho=0.7, gamma=0.5, pw=1.0):
+def run_gpu(R, values, cls, K=100, overwrite="dfsr", rho=0.7, gamma=0.5, pw=1.0, precision="fp64"):
     out, out_u8 = R.fsr_blocks(dev(values, torch.float32), dev(cls),
                                R.FSRParams(iters=K, overwrite=overwrite, rho=rho, gamma=gamma,
-                                           proj_weight=pw))
+                                           proj_weight=pw, precision=precision))
     return host(out), host(out_u8)
 
 
@@ -29,14 +29,15 @@ def frame(seed, H, W, kind="dynamic"):
 
 @pytest.mark.parametrize("H,W,kind,K", [(128, 128, "dynamic", 100), (128, 128, "fixed", 100),
                                         (132, 100, "dynamic", 100), (68, 36, "dynamic", 300)])
-def test_fsr_parity(H, W, kind, K):
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_fsr_parity(H, W, kind, K, precision):
     R = need_gpu()
     f, m, meas = frame(3, H, W, kind)
     vals = meas.astype(np.float64)
     ora, gaps = O.fsr_frame(vals, m, K=K)
-    out, out_u8 = run_gpu(R, vals, m, K=K)
+    out, out_u8 = run_gpu(R, vals, m, K=K, precision=precision)
     worst, namb, nb = compare_fsr(out, ora, gaps)
-    print(f"FSR {H}x{W} {kind} K={K}: max|gpu-oracle| {worst:.2e} over unambiguous blocks, "
+    print(f"FSR {precision} {H}x{W} {kind} K={K}: max|gpu-oracle| {worst:.2e} over unambiguous blocks, "
           f"{namb}/{nb} tie-ambiguous")
     assert worst <= FSR_TOL
     assert namb <= AMB_MAX * nb
@@ -46,7 +47,8 @@ def test_fsr_parity(H, W, kind, K):
     assert (out[m == 1] == meas[m == 1]).all()
 
 
-def test_fsr_projected_classes_both_overwrites():
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_fsr_projected_classes_both_overwrites(precision):
     R = need_gpu()
     f, m, meas = frame(4, 96, 64)
     rng = np.random.default_rng(0)
@@ -59,7 +61,7 @@ def test_fsr_projected_classes_both_overwrites():
     for ow in ("dfsr", "rfsr"):
         for pw in (1.0, 0.5):
             ora, gaps = O.fsr_frame(vals, cls, K=60, overwrite=ow, proj_weight=pw)
-            out, _ = run_gpu(R, vals, cls, K=60, overwrite=ow, pw=pw)
+            out, _ = run_gpu(R, vals, cls, K=60, overwrite=ow, pw=pw, precision=precision)
             worst, namb, nb = compare_fsr(out, ora, gaps)
             assert worst <= FSR_TOL, (ow, pw, worst)
             if ow == "rfsr":
@@ -67,48 +69,52 @@ def test_fsr_projected_classes_both_overwrites():
 
 
 @pytest.mark.parametrize("K", [1, 20])
-def test_fsr_constant_closed_form(K):
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_fsr_constant_closed_form(K, precision):
     """Constant scene: DC is chosen every iteration, model c (1 - (1-gamma)^K)."""
     R = need_gpu()
     rng = np.random.default_rng(1)
     m = synth.fixed_mask(64, 64, rng)
     vals = np.where(m == 1, 100.0, 0.0)
-    out, _ = run_gpu(R, vals, m, K=K)
+    out, _ = run_gpu(R, vals, m, K=K, precision=precision)
     expect = 100.0 * (1 - 0.5 ** K)
     assert np.max(np.abs(out[m == 0] - expect)) < 1e-3
     assert (out[m == 1] == 100.0).all()
 
 
-def test_fsr_garbage_invariance_and_determinism():
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_fsr_garbage_invariance_and_determinism(precision):
     R = need_gpu()
     f, m, meas = frame(5, 64, 96)
     vals = meas.astype(np.float32)
-    out1, _ = run_gpu(R, vals, m)
+    out1, _ = run_gpu(R, vals, m, precision=precision)
     g = vals.copy()
     g[m == 0] = np.nan
-    out2, _ = run_gpu(R, g, m)
-    out3, _ = run_gpu(R, vals, m)
+    out2, _ = run_gpu(R, g, m, precision=precision)
+    out3, _ = run_gpu(R, vals, m, precision=precision)
     assert np.array_equal(out1, out2) and np.array_equal(out1, out3)
 
 
-def test_fsr_edge_cases():
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_fsr_edge_cases(precision):
     R = need_gpu()
     # single block frame
     m = np.array([[1, 0, 1, 0], [0, 0, 0, 0], [0, 1, 0, 1], [0, 0, 0, 0]], np.uint8)
     vals = np.where(m == 1, 50.0, 0.0)
     ora, _ = O.fsr_frame(vals, m, K=10)
-    out, _ = run_gpu(R, vals, m, K=10)
+    out, _ = run_gpu(R, vals, m, K=10, precision=precision)
     assert np.max(np.abs(out - ora)) < FSR_TOL
     # K = 0: model 0 except the overwrite
     f, m2, meas = frame(6, 32, 32)
-    out0, _ = run_gpu(R, meas.astype(np.float32), m2, K=0)
+    out0, _ = run_gpu(R, meas.astype(np.float32), m2, K=0, precision=precision)
     assert (out0[m2 == 0] == 0).all() and (out0[m2 == 1] == meas[m2 == 1]).all()
     # no samples at all
-    z, _ = run_gpu(R, np.zeros((8, 8), np.float32), np.zeros((8, 8), np.uint8), K=5)
+    z, _ = run_gpu(R, np.zeros((8, 8), np.float32), np.zeros((8, 8), np.uint8), K=5, precision=precision)
     assert (z == 0).all()
 
 
-def test_fsr_full_hd_sampled_blocks():
+@pytest.mark.parametrize("precision", FLOAT64_FORMS)
+def test_fsr_full_hd_sampled_blocks(precision):
     """1920x1080 frame in the benchmark's launch configuration; the oracle
     recomputes a seeded sample of blocks one by one."""
     R = need_gpu()
@@ -116,7 +122,7 @@ def test_fsr_full_hd_sampled_blocks():
     f, m = synth.workload_c2(n=1, h=H, w=W)
     meas = synth.measured(f, m)[0]
     vals = meas.astype(np.float64)
-    out, _ = run_gpu(R, vals, m[0], K=100)
+    out, _ = run_gpu(R, vals, m[0], K=100, precision=precision)
     rng = np.random.default_rng(7)
     blocks = np.stack([rng.integers(0, H // 4, 256), rng.integers(0, W // 4, 256)], axis=1)
     blocks[:4] = [[0, 0], [H // 4 - 1, W // 4 - 1], [0, W // 4 - 1], [H // 4 - 1, 0]]
@@ -124,7 +130,7 @@ def test_fsr_full_hd_sampled_blocks():
     got = np.stack([out[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4] for bi, bj in blocks])
     d = np.abs(got - ora_b).max(axis=(1, 2))
     amb = gaps < TAU_FP64
-    print(f"1080p sample: max {d[~amb].max():.2e}, ambiguous {amb.sum()}/256")
+    print(f"1080p sample ({precision}): max {d[~amb].max():.2e}, ambiguous {amb.sum()}/256")
     assert d[~amb].max() <= FSR_TOL
     assert amb.sum() <= AMB_MAX * 256
 
