@@ -495,8 +495,9 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--pool", type=int, default=8, help="distinct synthetic frames per size and mask kind")
-    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3", "fp32", "mixed"], default="fp64",
-                    help="FSR arithmetic of the batched server (the plain loops are fp64 and fp32)")
+    ap.add_argument("--precision", choices=["fp64", "bf16x3", "fp16x3", "fp32", "mixed"], default="mixed",
+                    help="FSR arithmetic of the batched server (default mixed: the float64 model's result; "
+                         "the plain loops are fp64 and fp32)")
     a = ap.parse_args(argv)
 
     import numpy as np

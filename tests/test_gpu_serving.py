@@ -37,11 +37,13 @@ def alone(data, R, me, fsr):
     return res
 
 
-@pytest.mark.parametrize("mode,arrivals", [("batch", "burst"), ("batch", "poisson"), ("frame", "poisson")])
-def test_served_results_equal_alone(mode, arrivals):
+@pytest.mark.parametrize("mode,arrivals,precision", [("batch", "burst", "fp64"), ("batch", "poisson", "fp64"),
+                                                     ("frame", "poisson", "fp64"), ("batch", "burst", "mixed"),
+                                                     ("batch", "poisson", "mixed")])
+def test_served_results_equal_alone(mode, arrivals, precision):
     R = need_gpu()
     from paper_2203_09200_amd import serving as S
-    me, fsr = R.MEParams(search=5, check="nnc_frmc"), R.FSRParams(iters=30)
+    me, fsr = R.MEParams(search=5, check="nnc_frmc"), R.FSRParams(iters=30, precision=precision)
     data = stream_data()
     ref = alone(data, R, me, fsr)
 
