@@ -59,6 +59,15 @@ def psnr(ref, test, border=40):
     return float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)
 
 
+FORM_SUFFIX = {"fp64": "", "fp32": ", FSR all float32", "mixed": ", FSR float32 with float64 for near-tie blocks"}
+
+
+def dtype_of(precision):
+    """The arithmetic type the FSR path computes in, per precision option."""
+    return {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 for near-tie blocks)"}.get(
+        precision, f"f64 (block DFT {precision}, float32 accumulate)")
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -318,14 +327,14 @@ def run_multistream(a, dev):
         "n_gpus": 1, "steps": a.steps, "warmup": warm,
         "ms_per_step": round(elapsed / a.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32"}.get(a.precision,
-                                                     f"f64 (block DFT {a.precision}, float32 accumulate)"),
+        "dtype": dtype_of(a.precision),
         "data": "synthetic (seeded smooth texture, 8x8 translating regions, 5% occluders) per stream",
         "config": {"workload": f"48 streams (16x352x288, 16x1280x720, 12x1920x1080, 4x3840x2160), "
                                f"{T} frames cycled, even streams fixed mask / odd dynamic, D-FSR + "
                                f"{a.check.upper().replace('_', '+')}, R={a.search}, K={a.iters}, 3 references, "
                                f"one batch per time step" + (", pipelined time steps" if pipelined else
                                                              "" if a.no_graphs else ", graph replay")
+                               + FORM_SUFFIX.get(a.precision, f", block DFT {a.precision}")
                                + (f", concealed weighting {a.concealed}" if a.concealed else ""),
                    "streams": len(sizes), "hr_px_per_step": px_step, "parallelism": "single GPU",
                    "pipelined": pipelined},
@@ -484,6 +493,11 @@ def run(a, pool, cores):
                 "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "flops_per_launch": flops, "avg_launch_ms": round(fsr_avg_s * 1e3, 4)}
+    if f32:
+        # the published FP32 vector rate counts packed FMAs (two per lane and
+        # instruction); this library is built without packed FP32, whose FMA
+        # rate is that of FP64
+        roofline["frac_of_unpacked_fp32"] = round(achieved / PEAK_FP64_VECTOR_TFLOPS, 4)
     if reruns is not None:
         n_re = int(reruns.item())
         # frame 0 has no references: its FSR input is the measured frame, so the
@@ -533,15 +547,12 @@ def run(a, pool, cores):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32 (f64 for near-tie blocks)"}.get(
-            a.precision, f"f64 (block DFT {a.precision}, float32 accumulate)"),
+        "dtype": dtype_of(a.precision),
         "data": "synthetic (seeded smooth texture, 8x8 translating regions, 5% occluders)",
         "config": {"workload": f"{W}x{H} uint8, {F} frames, dynamic quarter mask, D-FSR + "
                                f"{a.check.upper().replace('_', '+')}, R={a.search}, T=4, "
                                f"4x4 blocks, 32x32 support, rho=0.7, gamma=0.5, K={a.iters}, 3 references"
-                               + {"fp64": "", "fp32": ", FSR all float32",
-                                  "mixed": ", FSR float32 with float64 for near-tie blocks"}.get(a.precision,
-                                                                              f", block DFT {a.precision}")
+                               + FORM_SUFFIX.get(a.precision, f", block DFT {a.precision}")
                                + (", conjugate-pair FSR" if a.pairs else "")
                                + (f", concealed weighting {a.concealed}" if a.concealed else "")
                                + (f", frequency prior sigma {a.prior}" if a.prior else "")

@@ -1,7 +1,7 @@
 """Small drivers to run under rocprofv3 (counter and trace collection).
 
     python -m paper_2203_09200_amd.profiling fsr  [--reps 3] [--delta D] [--precision P] [--iters K ...]
-                                                               # FSR kernel, 1080p workload frame
+                                                   [--mixed-bound A]   # FSR kernel, 1080p workload frame
     python -m paper_2203_09200_amd.profiling copy [--mib 1024] # plain device copy of known size
 
 `fsr` launches fsr_blocks on one frame of the 1920x1080 benchmark workload
@@ -51,7 +51,7 @@ def kernel_digest(precision: str = "fp64") -> str:
     return h.hexdigest()
 
 
-def run_fsr(reps: int, delta: float = 0.0, precision: str = "fp64", iters=(100,)):
+def run_fsr(reps: int, delta: float = 0.0, precision: str = "fp64", iters=(100,), mixed_bound=None):
     import numpy as np
     import torch
     sys.path.insert(0, ROOT)
@@ -63,15 +63,25 @@ def run_fsr(reps: int, delta: float = 0.0, precision: str = "fp64", iters=(100,)
     c = torch.from_numpy(m[0]).cuda()
     for K in iters:
         prm = R.FSRParams(iters=K, concealed_weight=delta, precision=precision)
+        if mixed_bound is not None:
+            prm.mixed_bound = mixed_bound
+        cnt = None
+        if precision == "mixed":
+            cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
         R.fsr_blocks(v, c, prm)
         torch.cuda.synchronize()
+        prm.rerun_blocks = cnt
         e0, e1 = R.Event(), R.Event()
         e0.record()
         for _ in range(reps):
             R.fsr_blocks(v, c, prm)
         e1.record()
+        extra = ""
+        if cnt is not None:
+            nb = (v.shape[0] // 4) * (v.shape[1] // 4)
+            extra = f", bound {prm.mixed_bound}: {int(cnt.item()) / reps / nb:.2%} of the blocks recomputed in float64"
         print(f"fsr_blocks x{reps} done: {e0.elapsed_ms(e1) / reps:.3f} ms per 1080p frame "
-              f"(K {K}, delta {delta}, precision {precision})", flush=True)
+              f"(K {K}, delta {delta}, precision {precision}{extra})", flush=True)
 
 
 def run_copy(mib: int):
@@ -141,6 +151,7 @@ def main(argv=None):
     a1.add_argument("--precision", default="fp64")
     a1.add_argument("--iters", type=int, nargs="+", default=[100],
                     help="iteration counts to time in turn (K = 0 times the setup alone)")
+    a1.add_argument("--mixed-bound", type=float, default=None, help="near-tie bound a of the mixed form")
     a2 = sub.add_parser("copy")
     a2.add_argument("--mib", type=int, default=1024)
     a3 = sub.add_parser("record")
@@ -154,7 +165,7 @@ def main(argv=None):
     a3.add_argument("--precision", choices=sorted(FORMS), default="fp64")
     a = ap.parse_args(argv)
     if a.cmd == "fsr":
-        run_fsr(a.reps, a.delta, a.precision, a.iters)
+        run_fsr(a.reps, a.delta, a.precision, a.iters, a.mixed_bound)
     elif a.cmd == "copy":
         run_copy(a.mib)
     else:
